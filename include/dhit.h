@@ -1,0 +1,197 @@
+/*
+ * dhit.h - C ABI of the MI355X (gfx950) library for the per-time-step update
+ * of the lattice Boltzmann equation (LBE) and of the discrete unified
+ * gas-kinetic scheme (DUGKS) on a periodic cube, as compared in
+ * Wang, Wang & Guo, arXiv 1601.03815.
+ *
+ * General rules
+ *   - Every function returns a status code (DHIT_OK = 0, negative on error;
+ *     box_bytes and population_buffer_bytes return a byte count, or a
+ *     negative status).  No C++ exception crosses this boundary.  After an
+ *     error, dhit_last_error() returns a message for the calling thread.
+ *   - Units are lattice units: dx = 1, particle speed c = 1, RT = c_s^2 =
+ *     1/3 (Sec. IV.A).  The mean density rho0 is a parameter (the paper
+ *     uses 1); velocities are u = j / rho0.
+ *   - A box is an n^3 periodic grid of cells; cell (x, y, z) has flat index
+ *     idx = (z*n + y)*n + x (x fastest).  Host-side arrays passed to this
+ *     library are C arrays of double in that order: a scalar field is
+ *     [n^3], a vector field is [3][n^3], a population field is [19][n^3].
+ *   - Population order (D3Q19, Sec. II.A; the paper leaves it open, this
+ *     order is part of the ABI): q0 = (0,0,0); q1..q6 = +x, -x, +y, -y,
+ *     +z, -z; q7..q10 = (1,1,0), (-1,1,0), (1,-1,0), (-1,-1,0); q11..q14 =
+ *     (1,0,1), (-1,0,1), (1,0,-1), (-1,0,-1); q15..q18 = (0,1,1),
+ *     (0,-1,1), (0,1,-1), (0,-1,-1).
+ *   - Populations are the paper's density-fluctuation form: the discrete
+ *     equilibrium of Sec. II.A sums to drho, so f already excludes the
+ *     W_i rho0 background (the "deviation form").  FP32 boxes store these
+ *     same values in float.
+ *   - Ownership: a box owns its device state unless the caller supplies
+ *     the two population buffers (then the caller keeps ownership and must
+ *     keep them alive until destroy_box).  The caller owns all host arrays.
+ *   - Streams: all device work of a box is issued on params.stream (a
+ *     hipStream_t; NULL makes the library create one).  step_* calls are
+ *     asynchronous; calls that return host data synchronise that stream.
+ *   - Thread safety: one box must not be used from two threads at once;
+ *     different boxes are independent.
+ */
+#ifndef DHIT_H
+#define DHIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dhit_box dhit_box;
+
+enum dhit_status {
+    DHIT_OK = 0,
+    DHIT_EINVAL = -1,      /* bad argument (null pointer, size or parameter out of range) */
+    DHIT_ENOMEM = -2,      /* device or host allocation failed */
+    DHIT_EDEVICE = -3,     /* a HIP or hipFFT call failed */
+    DHIT_EMETHOD = -4,     /* step_lbe on a DUGKS box or step_dugks on an LBE box */
+    DHIT_ENONFINITE = -5   /* a global reduction became NaN or infinite (the run blew up) */
+};
+
+enum dhit_method {
+    DHIT_LBE_BGK = 0,      /* LBE with single-relaxation (BGK) collision, tau = 3 nu + 1/2 */
+    DHIT_LBE_MRT = 1,      /* LBE with the D3Q19 multiple-relaxation-time collision of Sec. II.B */
+    DHIT_DUGKS = 2         /* DUGKS finite-volume step of Sec. II.A, tau = nu / RT */
+};
+
+enum dhit_precision {
+    DHIT_FP64 = 0,         /* populations stored and updated in double */
+    DHIT_FP32 = 1          /* populations stored and updated in float, per-cell moment sums
+                              compensated, global reductions in double */
+};
+
+/* Kernel variant of a step.  DHIT_VARIANT_DEFAULT picks the fastest
+ * implementation; DHIT_VARIANT_TWO_PASS selects the two-kernel DUGKS step
+ * (cell transform to a scratch field, then the face loop), kept as a
+ * plainer cross-check of the fused kernel.  Ignored by LBE boxes. */
+enum dhit_variant { DHIT_VARIANT_DEFAULT = 0, DHIT_VARIANT_TWO_PASS = 1 };
+
+typedef struct dhit_params {
+    int32_t n;          /* cells per side, 4 <= n <= 1024 */
+    int32_t method;     /* enum dhit_method */
+    int32_t precision;  /* enum dhit_precision */
+    int32_t variant;    /* enum dhit_variant */
+    double nu;          /* kinematic viscosity, > 0 */
+    double rho0;        /* mean density, > 0 (paper: 1) */
+    double dt;          /* time step: LBE requires 1; DUGKS requires 0 < dt*sqrt(2) <= 1
+                           (CFL number dt*sqrt(2) of Sec. IV.A; the paper uses dt = 0.5) */
+    /* MRT relaxation rates, diagonal of S in Sec. II.B (used by DHIT_LBE_MRT only).
+     * s9 and s13 are normally 1/(3 nu + 1/2) (Sec. IV.A); default_params sets them so. */
+    double s1, s2, s4, s9, s10, s13, s16;
+    /* MRT equilibrium constants of Sec. II.B (paper: 0, -475/63, 0). */
+    double w_eps, w_epsj, w_xx;
+    void *stream;       /* hipStream_t, or NULL */
+    void *f_a, *f_b;    /* optional caller-owned device buffers, each of
+                           population_buffer_bytes(params) bytes and 256-byte aligned;
+                           both NULL makes the library allocate them */
+} dhit_params;
+
+/* Fill *out with the paper's parameters for an n^3 box (Sec. IV.A):
+ * rho0 = 1; dt = 1 (LBE) or 0.5 (DUGKS); s1 = 1.19, s2 = s10 = 1.4,
+ * s4 = 1.2, s16 = 1.98, s9 = s13 = 1/(3 nu + 1/2); w_eps = w_xx = 0,
+ * w_epsj = -475/63; variant default; stream and buffers NULL. */
+int32_t default_params(int32_t n, int32_t method, int32_t precision, double nu,
+                       dhit_params *out);
+
+/* Bytes of one population buffer (19 padded per-population arrays). */
+int64_t population_buffer_bytes(const dhit_params *p);
+
+/* Device bytes a box with these parameters needs: both population buffers
+ * (counted even when the caller supplies them), plus reduction scratch and,
+ * for DUGKS boxes of the two-pass variant, the transform scratch field.
+ * The spectrum work space is allocated on the first energy_spectrum call
+ * and is not included.  Used by schedulers to admit boxes by HBM budget. */
+int64_t box_bytes(const dhit_params *p);
+
+/* Create a box.  Validates *p; on success *out owns the new box. */
+int32_t create_box(const dhit_params *p, dhit_box **out);
+
+/* Destroy a box and free the device memory the library allocated. */
+int32_t destroy_box(dhit_box *b);
+
+/* Set the initial state from a velocity field u[3][n^3] (host) and an
+ * optional density-fluctuation field drho[n^3] (host, NULL = 0).
+ * BGK-LBE and DUGKS start from f = f^eq(drho, rho0 u) (Sec. II.A
+ * equilibrium; for DUGKS the tracked f~ equals f when Omega = 0); MRT-LBE
+ * starts from f = M^-1 m^eq (the fixed point of its collision, Sec. II.B).
+ * Resets the step counter and the reduction history.  Synchronous. */
+int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
+
+/* Advance an LBE box by nsteps >= 0 steps of dt = 1: fused pull
+ * streaming + collision (Sec. II.B evolution equation; BGK or MRT).  The
+ * stored state is the post-collision population field.  Each step ends
+ * with the global FP64 reduction (sum drho, sum jx, sum jy, sum jz,
+ * 1/2 sum |u|^2) of the new state, kept in the box's history.
+ * Asynchronous.  DHIT_EMETHOD on a DUGKS box. */
+int32_t step_lbe(dhit_box *b, int32_t nsteps);
+
+/* Advance a DUGKS box by nsteps >= 0 steps of dt (Sec. II.A finite-volume
+ * update): cell transform to f-bar-plus and f~+, face reconstruction with
+ * the half-step characteristic, face equilibrium, flux divergence.  The
+ * stored state is f~.  Same per-step reduction as step_lbe.
+ * Asynchronous.  DHIT_EMETHOD on an LBE box. */
+int32_t step_dugks(dhit_box *b, int32_t nsteps);
+
+/* Per-cell density fluctuation drho[n^3] and momentum j[3][n^3] (host,
+ * each optional) and the global sums[5] = (sum drho, sum jx, sum jy,
+ * sum jz, 1/2 sum |j/rho0|^2) of the current state (optional).  The
+ * moments do not depend on the storage phase (collision conserves them).
+ * Synchronous.  Returns DHIT_ENONFINITE if a sum is not finite. */
+int32_t moments(dhit_box *b, double *drho, double *j, double *sums);
+
+/* Global sums of the reductions run at the end of the last `count` steps,
+ * oldest first, into out[count][5]; count <= min(steps taken, 4096).
+ * Synchronous.  Returns DHIT_ENONFINITE if any of them is not finite. */
+int32_t sums_history(dhit_box *b, double *out, int32_t count);
+
+/* Energy spectrum and statistics of the current velocity field u = j/rho0
+ * (Sec. III): u_hat = DFT(u)/n^3 (hipFFT); E[k] for integer shells
+ * k = 0..kmax is the sum of 1/2 |u_hat|^2 over modes with round(|k|) = k;
+ * stats[4] (optional) = (K, eps, S, F): K = sum of 1/2 |u_hat|^2 over all
+ * modes, eps = 2 nu sum |kappa|^2 1/2 |u_hat|^2 with kappa = 2 pi k / n,
+ * S and F the direction-averaged velocity-derivative skewness and flatness
+ * from spectral derivatives (Nyquist component dropped).  0 <= kmax.
+ * Allocates its work space on the first call.  Synchronous. */
+int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats);
+
+/* Copy the stored population field to/from host f[19][n^3] (double; FP32
+ * boxes convert).  The stored phase is post-collision for LBE boxes and
+ * f~ for DUGKS boxes.  set_populations resets the step counter and the
+ * reduction history.  Synchronous. */
+int32_t get_populations(dhit_box *b, double *f);
+int32_t set_populations(dhit_box *b, const double *f);
+
+/* Number of steps taken since the last initialisation. */
+int64_t steps_taken(const dhit_box *b);
+
+/* Wait for all queued work of the box.  Returns DHIT_ENONFINITE if the
+ * newest reduction is not finite. */
+int32_t box_synchronize(dhit_box *b);
+
+/* Device pointer of the buffer that holds the current population field and
+ * its per-population stride in elements (for callers that read the state
+ * in place, e.g. from PyTorch).  Either output may be NULL. */
+int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
+
+/* Advance many boxes of one method and precision by nsteps steps, each step
+ * being one persistent kernel launch over a work list of tiles that spans
+ * all boxes (LBE) or one launch per phase (DUGKS), followed by one
+ * reduction launch for all boxes.  All boxes must share method and
+ * precision; work is issued on the first box's stream and the other boxes'
+ * streams are made to wait for it.  Results equal per-box steps. */
+int32_t step_batch(dhit_box **boxes, int32_t nbox, int32_t nsteps);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *dhit_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DHIT_H */

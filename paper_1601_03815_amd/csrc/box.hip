@@ -1,0 +1,422 @@
+// C ABI of the library (declared in include/dhit.h): parameter handling,
+// box lifetime, buffers, and the step loops.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lattice.hpp"
+#include "runtime.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+
+// hipGetLastError() reports the last failing HIP call of the thread, including
+// calls made outside this library (by the host program or another library
+// sharing the runtime) and calls whose status is deliberately ignored during
+// clean-up.  Every entry point clears that state first, so a launch check
+// inside the library reports the library's own launch.  DHIT_DEBUG=1 prints
+// what was cleared.
+void clear_stale_hip_error() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess && std::getenv("DHIT_DEBUG"))
+    std::fprintf(stderr, "dhit: cleared a pending HIP error at entry: %s\n", hipGetErrorString(e));
+}
+
+template <class F>
+int32_t guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    clear_stale_hip_error();
+    return f();
+  } catch (const dhit::Error &e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return DHIT_ENOMEM;
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return DHIT_EINVAL;
+  }
+}
+
+[[noreturn]] void fail(int32_t code, const std::string &m) { throw dhit::Error(code, m); }
+
+// Elements between consecutive population arrays: the cell count rounded up
+// to 256 bytes' worth of elements plus a 4 KiB shift, so that the 19 arrays
+// start at staggered offsets modulo large powers of two (cell counts such as
+// 256^3 would otherwise place all 19 streams on the same memory channels).
+int64_t padded_stride(int64_t ncell, size_t elem) {
+  const int64_t align = 256 / (int64_t)elem;
+  const int64_t shift = 4096 / (int64_t)elem;
+  return ((ncell + align - 1) / align) * align + shift;
+}
+
+void validate(const dhit_params &p) {
+  if (p.n < 4 || p.n > 1024) fail(DHIT_EINVAL, "n must be in [4, 1024]");
+  if (p.method < DHIT_LBE_BGK || p.method > DHIT_DUGKS) fail(DHIT_EINVAL, "unknown method");
+  if (p.precision != DHIT_FP64 && p.precision != DHIT_FP32) fail(DHIT_EINVAL, "unknown precision");
+  if (p.variant != DHIT_VARIANT_DEFAULT && p.variant != DHIT_VARIANT_TWO_PASS) fail(DHIT_EINVAL, "unknown variant");
+  if (!(p.nu > 0) || !std::isfinite(p.nu)) fail(DHIT_EINVAL, "nu must be positive and finite");
+  if (!(p.rho0 > 0) || !std::isfinite(p.rho0)) fail(DHIT_EINVAL, "rho0 must be positive and finite");
+  if (p.method == DHIT_DUGKS) {
+    if (!(p.dt > 0) || p.dt * std::sqrt(2.0) > 1.0 + 1e-12)
+      fail(DHIT_EINVAL, "DUGKS needs 0 < dt and CFL dt*sqrt(2) <= 1");
+  } else if (p.dt != 1.0) {
+    fail(DHIT_EINVAL, "LBE requires dt = 1 (dt = dx in lattice units)");
+  }
+  if ((p.f_a == nullptr) != (p.f_b == nullptr)) fail(DHIT_EINVAL, "f_a and f_b must both be given or both NULL");
+  if (p.f_a && ((reinterpret_cast<uintptr_t>(p.f_a) | reinterpret_cast<uintptr_t>(p.f_b)) & 255))
+    fail(DHIT_EINVAL, "caller buffers must be 256-byte aligned");
+  const double rates[] = {p.s1, p.s2, p.s4, p.s9, p.s10, p.s13, p.s16};
+  if (p.method == DHIT_LBE_MRT)
+    for (double s : rates)
+      if (!(s > 0 && s < 2)) fail(DHIT_EINVAL, "MRT rates must lie in (0, 2)");
+}
+
+void derive_step_params(dhit_box &b) {
+  const dhit_params &p = b.p;
+  dhit::StepParams &s = b.sp;
+  std::memset(&s, 0, sizeof(s));
+  s.n = b.n;
+  s.stride = b.stride;
+  s.rho0 = p.rho0;
+  s.inv_rho0 = 1.0 / p.rho0;
+  // BGK-LBE: nu = (tau - 1/2)/3 with dt = 1
+  s.omega = 1.0 / (3.0 * p.nu + 0.5);
+  // MRT: diagonal of S in the order of Sec. II.B, divided by the row norms
+  const double S[19] = {0, p.s1, p.s2, 0, p.s4, 0, p.s4, 0, p.s4, p.s9, p.s10, p.s9, p.s10,
+                        p.s13, p.s13, p.s13, p.s16, p.s16, p.s16};
+  for (int k = 0; k < 19; ++k) s.r[k] = dhit::mrt_conserved(k) ? 0.0 : S[k] / (double)dhit::mrt_norm(k);
+  s.w_eps = p.w_eps;
+  s.w_epsj = p.w_epsj;
+  s.w_xx = p.w_xx;
+  // DUGKS: tau = nu / RT
+  s.tau = 3.0 * p.nu;
+  s.dt = p.dt;
+  s.h = 0.5 * p.dt;
+  s.a_bp = (2.0 * s.tau - s.h) / (2.0 * s.tau + s.dt);
+  s.b_bp = 3.0 * s.h / (2.0 * s.tau + s.dt);
+  s.alpha = 2.0 * s.tau / (2.0 * s.tau + s.h);
+  s.beta = s.h / (2.0 * s.tau + s.h);
+}
+
+int64_t scratch_bytes_of(const dhit_params &p, int64_t pop_bytes) {
+  (void)p;
+  return pop_bytes;  // DUGKS transform field (allocated for every DUGKS box)
+}
+
+void check_finite(const double *s, int count) {
+  for (int i = 0; i < count; ++i)
+    if (!std::isfinite(s[i])) fail(DHIT_ENONFINITE, "a global reduction is not finite (the run blew up)");
+}
+
+void require_box(const dhit_box *b) {
+  if (!b) fail(DHIT_EINVAL, "null box");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t default_params(int32_t n, int32_t method, int32_t precision, double nu, dhit_params *out) {
+  return guarded([&]() -> int32_t {
+    if (!out) fail(DHIT_EINVAL, "null output");
+    dhit_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.method = method;
+    p.precision = precision;
+    p.variant = DHIT_VARIANT_DEFAULT;
+    p.nu = nu;
+    p.rho0 = 1.0;
+    p.dt = method == DHIT_DUGKS ? 0.5 : 1.0;
+    p.s1 = 1.19;
+    p.s2 = 1.4;
+    p.s4 = 1.2;
+    p.s9 = 1.0 / (3.0 * nu + 0.5);
+    p.s10 = 1.4;
+    p.s13 = p.s9;
+    p.s16 = 1.98;
+    p.w_eps = 0.0;
+    p.w_epsj = -475.0 / 63.0;
+    p.w_xx = 0.0;
+    *out = p;
+    return DHIT_OK;
+  });
+}
+
+int64_t population_buffer_bytes(const dhit_params *p) {
+  int64_t r = 0;
+  int32_t st = guarded([&]() -> int32_t {
+    if (!p) fail(DHIT_EINVAL, "null params");
+    if (p->n < 4 || p->n > 1024) fail(DHIT_EINVAL, "n must be in [4, 1024]");
+    const size_t elem = p->precision == DHIT_FP32 ? 4 : 8;
+    const int64_t ncell = (int64_t)p->n * p->n * p->n;
+    r = 19 * padded_stride(ncell, elem) * (int64_t)elem;
+    return DHIT_OK;
+  });
+  return st == DHIT_OK ? r : st;
+}
+
+int64_t box_bytes(const dhit_params *p) {
+  int64_t pop = population_buffer_bytes(p);
+  if (pop < 0) return pop;
+  const int64_t ncell = (int64_t)p->n * p->n * p->n;
+  const int64_t blocks = (ncell + 255) / 256;
+  int64_t total = 2 * pop + blocks * 5 * 8 + dhit::kHistoryCap * 5 * 8;
+  if (p->method == DHIT_DUGKS) total += scratch_bytes_of(*p, pop);
+  return total;
+}
+
+int32_t create_box(const dhit_params *pp, dhit_box **out) {
+  return guarded([&]() -> int32_t {
+    if (!pp || !out) fail(DHIT_EINVAL, "null argument");
+    *out = nullptr;
+    validate(*pp);
+    dhit_box *b = new dhit_box();
+    try {
+      b->p = *pp;
+      b->n = pp->n;
+      b->ncell = (int64_t)pp->n * pp->n * pp->n;
+      b->elem = pp->precision == DHIT_FP32 ? 4 : 8;
+      b->stride = padded_stride(b->ncell, b->elem);
+      const int64_t pop = 19 * b->stride * (int64_t)b->elem;
+      if (pp->stream) {
+        b->stream = static_cast<hipStream_t>(pp->stream);
+      } else {
+        DHIT_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+      }
+      if (pp->f_a) {
+        b->f[0] = pp->f_a;
+        b->f[1] = pp->f_b;
+        b->own_f = false;
+      } else {
+        b->own_f = true;
+        if (hipMalloc(&b->f[0], pop) != hipSuccess || hipMalloc(&b->f[1], pop) != hipSuccess)
+          fail(DHIT_ENOMEM, "cannot allocate population buffers");
+      }
+      b->max_blocks = dhit::cell_blocks(b->ncell);
+      if (hipMalloc(&b->partials, (size_t)b->max_blocks * 5 * sizeof(double)) != hipSuccess ||
+          hipMalloc(&b->hist, (size_t)dhit::kHistoryCap * 5 * sizeof(double)) != hipSuccess)
+        fail(DHIT_ENOMEM, "cannot allocate reduction buffers");
+      if (pp->method == DHIT_DUGKS) {
+        if (hipMalloc(&b->scratch, scratch_bytes_of(*pp, pop)) != hipSuccess)
+          fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
+      }
+      derive_step_params(*b);
+      // zero state until initialised
+      DHIT_HIP(hipMemsetAsync(b->f[0], 0, pop, b->stream));
+      DHIT_HIP(hipMemsetAsync(b->hist, 0, (size_t)dhit::kHistoryCap * 5 * sizeof(double), b->stream));
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+    } catch (...) {
+      destroy_box(b);
+      throw;
+    }
+    *out = b;
+    return DHIT_OK;
+  });
+}
+
+int32_t destroy_box(dhit_box *b) {
+  if (!b) return DHIT_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  dhit::spectrum_free(*b);
+  if (b->own_f) {
+    if (b->f[0]) (void)hipFree(b->f[0]);
+    if (b->f[1]) (void)hipFree(b->f[1]);
+  }
+  if (b->partials) (void)hipFree(b->partials);
+  if (b->hist) (void)hipFree(b->hist);
+  if (b->scratch) (void)hipFree(b->scratch);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return DHIT_OK;
+}
+
+int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!u) fail(DHIT_EINVAL, "null velocity field");
+    const size_t bytes = (size_t)b->ncell * sizeof(double);
+    double *du = nullptr, *dr = nullptr;
+    if (hipMalloc(&du, 3 * bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+    try {
+      if (drho && hipMalloc(&dr, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+      DHIT_HIP(hipMemcpyAsync(du, u, 3 * bytes, hipMemcpyHostToDevice, b->stream));
+      if (drho) DHIT_HIP(hipMemcpyAsync(dr, drho, bytes, hipMemcpyHostToDevice, b->stream));
+      b->cur = 0;
+      dhit::launch_init_equilibrium(*b, du, dr, b->f[0]);
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipFree(du);
+      if (dr) (void)hipFree(dr);
+      throw;
+    }
+    (void)hipFree(du);
+    if (dr) (void)hipFree(dr);
+    b->steps = 0;
+    return DHIT_OK;
+  });
+}
+
+static int32_t step_common(dhit_box *b, int32_t nsteps, bool lbe) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (nsteps < 0) fail(DHIT_EINVAL, "nsteps must be >= 0");
+    const bool is_lbe = b->p.method != DHIT_DUGKS;
+    if (is_lbe != lbe) fail(DHIT_EMETHOD, lbe ? "step_lbe called on a DUGKS box" : "step_dugks called on an LBE box");
+    for (int32_t s = 0; s < nsteps; ++s) {
+      double *slot = b->hist + (b->steps % dhit::kHistoryCap) * 5;
+      const void *src = b->f[b->cur];
+      void *dst = b->f[1 - b->cur];
+      if (lbe)
+        dhit::launch_lbe_step(*b, src, dst, slot);
+      else
+        dhit::launch_dugks_step(*b, src, dst, slot);
+      b->cur = 1 - b->cur;
+      b->steps++;
+    }
+    return DHIT_OK;
+  });
+}
+
+int32_t step_lbe(dhit_box *b, int32_t nsteps) { return step_common(b, nsteps, true); }
+int32_t step_dugks(dhit_box *b, int32_t nsteps) { return step_common(b, nsteps, false); }
+
+int32_t moments(dhit_box *b, double *drho, double *j, double *sums) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    const size_t bytes = (size_t)b->ncell * sizeof(double);
+    double *dd = nullptr, *dj = nullptr, *ds = nullptr;
+    auto cleanup = [&]() {
+      if (dd) (void)hipFree(dd);
+      if (dj) (void)hipFree(dj);
+      if (ds) (void)hipFree(ds);
+    };
+    try {
+      if (drho && hipMalloc(&dd, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate moments buffer");
+      if (j && hipMalloc(&dj, 3 * bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate moments buffer");
+      if (hipMalloc(&ds, 5 * sizeof(double)) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate moments buffer");
+      dhit::launch_moments(*b, b->f[b->cur], dd, dj, ds);
+      double hs[5];
+      DHIT_HIP(hipMemcpyAsync(hs, ds, sizeof(hs), hipMemcpyDeviceToHost, b->stream));
+      if (drho) DHIT_HIP(hipMemcpyAsync(drho, dd, bytes, hipMemcpyDeviceToHost, b->stream));
+      if (j) DHIT_HIP(hipMemcpyAsync(j, dj, 3 * bytes, hipMemcpyDeviceToHost, b->stream));
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+      if (sums) std::memcpy(sums, hs, sizeof(hs));
+      cleanup();
+      check_finite(hs, 5);
+    } catch (...) {
+      (void)hipStreamSynchronize(b->stream);
+      cleanup();
+      throw;
+    }
+    return DHIT_OK;
+  });
+}
+
+int32_t sums_history(dhit_box *b, double *out, int32_t count) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (count < 0 || (count > 0 && !out)) fail(DHIT_EINVAL, "bad output");
+    if (count > b->steps || count > dhit::kHistoryCap) fail(DHIT_EINVAL, "count exceeds the recorded history");
+    DHIT_HIP(hipStreamSynchronize(b->stream));
+    for (int32_t i = 0; i < count; ++i) {
+      const int64_t step = b->steps - count + i;
+      DHIT_HIP(hipMemcpy(out + 5 * i, b->hist + (step % dhit::kHistoryCap) * 5, 5 * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    }
+    check_finite(out, 5 * count);
+    return DHIT_OK;
+  });
+}
+
+int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (kmax < 0 || !E) fail(DHIT_EINVAL, "need E and kmax >= 0");
+    dhit::spectrum_compute(*b, E, kmax, stats);
+    return DHIT_OK;
+  });
+}
+
+int32_t get_populations(dhit_box *b, double *f) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!f) fail(DHIT_EINVAL, "null output");
+    const size_t bytes = (size_t)b->ncell * 19 * sizeof(double);
+    double *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate download buffer");
+    try {
+      dhit::launch_pack(*b, b->f[b->cur], d);
+      DHIT_HIP(hipMemcpyAsync(f, d, bytes, hipMemcpyDeviceToHost, b->stream));
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipFree(d);
+      throw;
+    }
+    (void)hipFree(d);
+    return DHIT_OK;
+  });
+}
+
+int32_t set_populations(dhit_box *b, const double *f) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!f) fail(DHIT_EINVAL, "null input");
+    const size_t bytes = (size_t)b->ncell * 19 * sizeof(double);
+    double *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+    try {
+      DHIT_HIP(hipMemcpyAsync(d, f, bytes, hipMemcpyHostToDevice, b->stream));
+      b->cur = 0;
+      dhit::launch_unpack(*b, d, b->f[0]);
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipFree(d);
+      throw;
+    }
+    (void)hipFree(d);
+    b->steps = 0;
+    return DHIT_OK;
+  });
+}
+
+int64_t steps_taken(const dhit_box *b) { return b ? b->steps : DHIT_EINVAL; }
+
+int32_t box_synchronize(dhit_box *b) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    DHIT_HIP(hipStreamSynchronize(b->stream));
+    if (b->steps > 0) {
+      double s[5];
+      DHIT_HIP(hipMemcpy(s, b->hist + ((b->steps - 1) % dhit::kHistoryCap) * 5, sizeof(s), hipMemcpyDeviceToHost));
+      check_finite(s, 5);
+    }
+    return DHIT_OK;
+  });
+}
+
+int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (ptr) *ptr = b->f[b->cur];
+    if (stride) *stride = b->stride;
+    return DHIT_OK;
+  });
+}
+
+const char *dhit_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Device helpers shared by the LBE, DUGKS and diagnostics kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace dhit {
+
+constexpr int kBlock = 256;            // threads per block of the streaming kernels
+constexpr int kWaves = kBlock / 64;    // 64-wide wavefronts per block
+constexpr int kNumSums = 5;            // sum drho, sum jx, sum jy, sum jz, 1/2 sum |u|^2
+
+// Compensated summation (Knuth's TwoSum) used for the per-cell moment sums
+// of FP32 boxes: s + c carries the sum with the rounding error of every
+// addition accumulated in c.
+template <typename Real>
+struct CompSum {
+  Real s = Real(0), c = Real(0);
+  __device__ __forceinline__ void add(Real x) {
+    Real t = s + x;
+    Real z = t - s;
+    c += (s - (t - z)) + (x - z);
+    s = t;
+  }
+  __device__ __forceinline__ void sub(Real x) { add(-x); }
+  __device__ __forceinline__ Real value() const { return s + c; }
+};
+
+// Moments of one cell: drho = sum f, j = sum xi f (Sec. II.A / II.B).
+// Double: plain sums.  Float: compensated sums.
+template <typename Real>
+__device__ __forceinline__ void cell_moments(const Real (&f)[kQ], Real &drho, Real &jx, Real &jy, Real &jz) {
+  if constexpr (std::is_same<Real, double>::value) {
+    double r = 0, ax = 0, ay = 0, az = 0;
+    static_for<kQ>([&](auto q) {
+      r += f[q];
+      if constexpr (kCx[q] == 1) ax += f[q];
+      if constexpr (kCx[q] == -1) ax -= f[q];
+      if constexpr (kCy[q] == 1) ay += f[q];
+      if constexpr (kCy[q] == -1) ay -= f[q];
+      if constexpr (kCz[q] == 1) az += f[q];
+      if constexpr (kCz[q] == -1) az -= f[q];
+    });
+    drho = r; jx = ax; jy = ay; jz = az;
+  } else {
+    CompSum<Real> r, ax, ay, az;
+    static_for<kQ>([&](auto q) {
+      r.add(f[q]);
+      if constexpr (kCx[q] == 1) ax.add(f[q]);
+      if constexpr (kCx[q] == -1) ax.sub(f[q]);
+      if constexpr (kCy[q] == 1) ay.add(f[q]);
+      if constexpr (kCy[q] == -1) ay.sub(f[q]);
+      if constexpr (kCz[q] == 1) az.add(f[q]);
+      if constexpr (kCz[q] == -1) az.sub(f[q]);
+    });
+    drho = r.value(); jx = ax.value(); jy = ay.value(); jz = az.value();
+  }
+}
+
+// Discrete incompressible equilibrium of Sec. II.A with RT = 1/3:
+// f_q^eq = W_q [drho + rho0 (3 xi.u + 9/2 (xi.u)^2 - 3/2 |u|^2)], u = j/rho0.
+template <typename Real>
+__device__ __forceinline__ void equilibrium(Real drho, Real jx, Real jy, Real jz, Real rho0, Real inv_rho0,
+                                            Real (&feq)[kQ]) {
+  const Real ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
+  const Real uu = ux * ux + uy * uy + uz * uz;
+  const Real base = drho - Real(1.5) * rho0 * uu;
+  static_for<kQ>([&](auto q) {
+    constexpr Real w = Real(kWeight(q));
+    Real xu = Real(0);
+    if constexpr (kCx[q] == 1) xu += ux;
+    if constexpr (kCx[q] == -1) xu -= ux;
+    if constexpr (kCy[q] == 1) xu += uy;
+    if constexpr (kCy[q] == -1) xu -= uy;
+    if constexpr (kCz[q] == 1) xu += uz;
+    if constexpr (kCz[q] == -1) xu -= uz;
+    feq[q] = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
+  });
+}
+
+// Sum of five doubles over the block; thread 0 gets the block total.
+// Deterministic: fixed shuffle tree inside each wavefront, then the
+// wavefront totals in wavefront order.
+__device__ __forceinline__ void block_sum5(double (&v)[kNumSums], double (*smem)[kNumSums]) {
+  static_for<kNumSums>([&](auto i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  });
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    static_for<kNumSums>([&](auto i) { smem[wave][i] = v[i]; });
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    static_for<kNumSums>([&](auto i) {
+      double s = smem[0][i];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s += smem[w][i];
+      v[i] = s;
+    });
+  }
+}
+
+// Per-cell contributions to the five global sums.
+template <typename Real>
+__device__ __forceinline__ void sums_of_cell(Real drho, Real jx, Real jy, Real jz, double inv_rho0,
+                                             double (&v)[kNumSums]) {
+  const double x = (double)jx, y = (double)jy, z = (double)jz;
+  v[0] += (double)drho;
+  v[1] += x;
+  v[2] += y;
+  v[3] += z;
+  v[4] += 0.5 * (x * x + y * y + z * z) * inv_rho0 * inv_rho0;
+}
+
+// Writes the block's five sums to partials laid out [5][nblocks].
+__device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], double *partials, int nblocks,
+                                                     int block) {
+  __shared__ double smem[kBlock / 64][kNumSums];
+  block_sum5(v, smem);
+  if (threadIdx.x == 0) {
+    static_for<kNumSums>([&](auto i) { partials[(int64_t)i * nblocks + block] = v[i]; });
+  }
+}
+
+// Flat-index offsets of the +-1 neighbours along one axis with periodic
+// wrap: up = offset of coordinate+1, dn = offset of coordinate-1.
+struct AxisOff {
+  int up, dn;
+};
+__device__ __forceinline__ AxisOff axis_offsets(int c, int n, int unit) {
+  AxisOff o;
+  o.up = (c == n - 1) ? -(n - 1) * unit : unit;
+  o.dn = (c == 0) ? (n - 1) * unit : -unit;
+  return o;
+}
+
+}  // namespace dhit

@@ -1,0 +1,152 @@
+// DUGKS time step (Sec. II.A finite-volume update).
+//
+// With tau = nu/RT, h = dt/2, the tracked field is f~.  Per cell:
+//   moments of f~ -> f^eq -> fbp = a f~ + b f^eq, a = (2tau-h)/(2tau+dt),
+//   b = 3h/(2tau+dt);  f~+ = 4/3 fbp - 1/3 f~.
+// Per face between L and R = L + e_d, for all 19 populations:
+//   fbar = (fbp_L + fbp_R)/2 - h [xi_d (fbp_R - fbp_L)
+//          + sum_{t != d} xi_t (G_t(L) + G_t(R))/4],  G_t(c) = fbp(c+e_t) - fbp(c-e_t)
+//   face moments of fbar -> f^eq_face -> f_face = alpha fbar + beta f^eq_face,
+//   alpha = 2tau/(2tau+h), beta = h/(2tau+h).
+// Update: f~(t+dt) = f~+ - dt sum_d xi_d (f_face(+d) - f_face(-d))   (dx = 1).
+//
+// This file holds the two-pass form: a transform kernel writes fbp to a
+// scratch field, then a face kernel evaluates the six faces of each cell
+// from that field (through the caches) and writes the update.
+#include "collision.hpp"
+
+namespace dhit {
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void dugks_transform_kernel(const Real *__restrict__ ft, Real *__restrict__ fbp,
+                                                                 StepParams p, int ncell) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  const int64_t stride = p.stride;
+  Real f[kQ];
+  static_for<kQ>([&](auto q) { f[q] = ft[(int64_t)q * stride + cell]; });
+  Real drho, jx, jy, jz, feq[kQ];
+  cell_moments<Real>(f, drho, jx, jy, jz);
+  equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
+  const Real a = Real(p.a_bp), b = Real(p.b_bp);
+  static_for<kQ>([&](auto q) { fbp[(int64_t)q * stride + cell] = a * f[q] + b * feq[q]; });
+}
+
+// Offsets of the 3x3x3 neighbourhood of a cell: off(dx,dy,dz) = X[dx] + Y[dy] + Z[dz].
+struct Nbr {
+  int X[3], Y[3], Z[3];  // index 0 = -1, 1 = 0, 2 = +1
+  __device__ __forceinline__ int at(int dx, int dy, int dz) const { return X[dx + 1] + Y[dy + 1] + Z[dz + 1]; }
+};
+
+// Face f (all fluxing populations) of the face at side s (+1 / -1) of the
+// cell along axis D; accumulates s * xi_D * f_face into acc.
+template <int D, int S, typename Real>
+__device__ __forceinline__ void face_accumulate(const Real *__restrict__ fbp, int cell, const Nbr &nb,
+                                                const StepParams &p, Real (&acc)[kQ]) {
+  const int64_t stride = p.stride;
+  // L = cell + (S == -1 ? -e_D : 0), R = L + e_D
+  constexpr int l = (S == -1) ? -1 : 0;
+  constexpr int r = l + 1;
+  auto off = [&](int a, int tb, int tc) {  // offset of (a along D, tb, tc along the two tangents)
+    int d[3] = {0, 0, 0};
+    d[D] = a;
+    constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    d[T1] = tb;
+    d[T2] = tc;
+    return nb.at(d[0], d[1], d[2]);
+  };
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const Real h = Real(p.h);
+  Real fbar[kQ];
+  static_for<kQ>([&](auto q) {
+    const Real *fq = fbp + (int64_t)q * stride + cell;
+    const Real fl = fq[off(l, 0, 0)], fr = fq[off(r, 0, 0)];
+    const Real sd = fr - fl;
+    Real tang = Real(0);
+    if constexpr (cdir(q, T1) != 0) {
+      const Real st = Real(0.25) * ((fq[off(l, 1, 0)] - fq[off(l, -1, 0)]) + (fq[off(r, 1, 0)] - fq[off(r, -1, 0)]));
+      tang += Real(cdir(q, T1)) * st;
+    }
+    if constexpr (cdir(q, T2) != 0) {
+      const Real st = Real(0.25) * ((fq[off(l, 0, 1)] - fq[off(l, 0, -1)]) + (fq[off(r, 0, 1)] - fq[off(r, 0, -1)]));
+      tang += Real(cdir(q, T2)) * st;
+    }
+    fbar[q] = (fl + Real(0.5) * sd) - h * (Real(cdir(q, D)) * sd + tang);
+  });
+  Real drho, jx, jy, jz, feq[kQ];
+  cell_moments<Real>(fbar, drho, jx, jy, jz);
+  equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
+  const Real al = Real(p.alpha), be = Real(p.beta);
+  static_for<kQ>([&](auto q) {
+    if constexpr (cdir(q, D) != 0) {
+      const Real ff = al * fbar[q] + be * feq[q];
+      if constexpr (S * cdir(q, D) > 0) acc[q] += ff;
+      else acc[q] -= ff;
+    }
+  });
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restrict__ ft, const Real *__restrict__ fbp,
+                                                            Real *__restrict__ out, StepParams p, int ncell,
+                                                            double *__restrict__ partials) {
+  const int n = p.n;
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  if (cell < ncell) {
+    const int x = cell % n;
+    const int t = cell / n;
+    const int y = t % n;
+    const int z = t / n;
+    const AxisOff ox = axis_offsets(x, n, 1), oy = axis_offsets(y, n, n), oz = axis_offsets(z, n, n * n);
+    Nbr nb;
+    nb.X[0] = ox.dn; nb.X[1] = 0; nb.X[2] = ox.up;
+    nb.Y[0] = oy.dn; nb.Y[1] = 0; nb.Y[2] = oy.up;
+    nb.Z[0] = oz.dn; nb.Z[1] = 0; nb.Z[2] = oz.up;
+    Real acc[kQ];
+    static_for<kQ>([&](auto q) { acc[q] = Real(0); });
+    face_accumulate<0, 1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<0, -1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<1, 1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<1, -1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<2, 1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<2, -1, Real>(fbp, cell, nb, p, acc);
+    const int64_t stride = p.stride;
+    const Real dt = Real(p.dt);
+    Real o[kQ];
+    static_for<kQ>([&](auto q) {
+      const Real bp = fbp[(int64_t)q * stride + cell];
+      const Real tl = ft[(int64_t)q * stride + cell];
+      o[q] = (Real(4.0 / 3.0) * bp - Real(1.0 / 3.0) * tl) - dt * acc[q];
+      out[(int64_t)q * stride + cell] = o[q];
+    });
+    Real drho, jx, jy, jz;
+    cell_moments<Real>(o, drho, jx, jy, jz);
+    sums_of_cell<Real>(drho, jx, jy, jz, p.inv_rho0, v);
+  }
+  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+}
+
+template <typename Real>
+static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  const int blocks = cell_blocks(b.ncell);
+  const Real *s = static_cast<const Real *>(src);
+  Real *d = static_cast<Real *>(dst);
+  Real *bp = static_cast<Real *>(b.scratch);
+  hipLaunchKernelGGL((dugks_transform_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, b.sp,
+                     (int)b.ncell);
+  DHIT_HIP(hipGetLastError());
+  hipLaunchKernelGGL((dugks_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
+                     (int)b.ncell, b.partials);
+  DHIT_HIP(hipGetLastError());
+  launch_finalize_sums(b.stream, b.partials, blocks, sums_out);
+}
+
+void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  if (b.p.precision == DHIT_FP64)
+    dugks_two_pass<double>(b, src, dst, sums_out);
+  else
+    dugks_two_pass<float>(b, src, dst, sums_out);
+}
+
+}  // namespace dhit

@@ -1,0 +1,169 @@
+// Field kernels around the time steps: initial equilibrium state, moments,
+// conversion between the stored state and host-order double arrays, and
+// the deterministic finalisation of the per-step global sums.
+#include "collision.hpp"
+
+namespace dhit {
+
+// f = f^eq(drho, rho0 u) (BGK-LBE, DUGKS) or f = M^-1 m^eq (MRT-LBE).
+template <typename Real, bool Mrt>
+__global__ __launch_bounds__(kBlock) void init_kernel(const double *__restrict__ u, const double *__restrict__ drho,
+                                                      Real *__restrict__ f, StepParams p, int ncell) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  const Real r = drho ? Real(drho[cell]) : Real(0);
+  const Real jx = Real(p.rho0 * u[cell]);
+  const Real jy = Real(p.rho0 * u[(int64_t)ncell + cell]);
+  const Real jz = Real(p.rho0 * u[2 * (int64_t)ncell + cell]);
+  Real fe[kQ];
+  if constexpr (Mrt)
+    mrt_equilibrium_populations<Real>(r, jx, jy, jz, p, fe);
+  else
+    equilibrium<Real>(r, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), fe);
+  static_for<kQ>([&](auto q) { f[(int64_t)q * p.stride + cell] = fe[q]; });
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void moments_kernel(const Real *__restrict__ f, double *__restrict__ drho,
+                                                         double *__restrict__ j, StepParams p, int ncell,
+                                                         double *__restrict__ partials) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  if (cell < ncell) {
+    Real g[kQ];
+    static_for<kQ>([&](auto q) { g[q] = f[(int64_t)q * p.stride + cell]; });
+    Real r, jx, jy, jz;
+    cell_moments<Real>(g, r, jx, jy, jz);
+    if (drho) drho[cell] = (double)r;
+    if (j) {
+      j[cell] = (double)jx;
+      j[(int64_t)ncell + cell] = (double)jy;
+      j[2 * (int64_t)ncell + cell] = (double)jz;
+    }
+    sums_of_cell<Real>(r, jx, jy, jz, p.inv_rho0, v);
+  }
+  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+}
+
+// u = j / rho0 as double [3][ncell].
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void velocity_kernel(const Real *__restrict__ f, double *__restrict__ u,
+                                                          StepParams p, int ncell) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  Real g[kQ];
+  static_for<kQ>([&](auto q) { g[q] = f[(int64_t)q * p.stride + cell]; });
+  Real r, jx, jy, jz;
+  cell_moments<Real>(g, r, jx, jy, jz);
+  u[cell] = (double)jx * p.inv_rho0;
+  u[(int64_t)ncell + cell] = (double)jy * p.inv_rho0;
+  u[2 * (int64_t)ncell + cell] = (double)jz * p.inv_rho0;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void pack_kernel(const Real *__restrict__ f, double *__restrict__ out,
+                                                      int64_t stride, int64_t ncell) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ncell * kQ) return;
+  const int64_t q = i / ncell, c = i - q * ncell;
+  out[i] = (double)f[q * stride + c];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void unpack_kernel(const double *__restrict__ in, Real *__restrict__ f,
+                                                        int64_t stride, int64_t ncell) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ncell * kQ) return;
+  const int64_t q = i / ncell, c = i - q * ncell;
+  f[q * stride + c] = (Real)in[i];
+}
+
+// Sums the [5][nblocks] partials in a fixed order: thread t takes blocks
+// t, t + 1024, ... in order, then a fixed tree over the threads.
+__global__ __launch_bounds__(1024) void finalize_sums_kernel(const double *__restrict__ partials, int nblocks,
+                                                             double *__restrict__ out) {
+  __shared__ double smem[16][kNumSums];
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 1024) {
+    static_for<kNumSums>([&](auto i) { v[i] += partials[(int64_t)i * nblocks + b]; });
+  }
+  block_sum5(v, smem);
+  if (threadIdx.x == 0) {
+    static_for<kNumSums>([&](auto i) { out[i] = v[i]; });
+  }
+}
+
+void launch_finalize_sums(hipStream_t s, const double *partials, int nblocks, double *out) {
+  hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, s, partials, nblocks, out);
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst) {
+  const int blocks = cell_blocks(b.ncell);
+  const bool mrt = b.p.method == DHIT_LBE_MRT;
+  if (b.p.precision == DHIT_FP64) {
+    if (mrt)
+      hipLaunchKernelGGL((init_kernel<double, true>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
+                         static_cast<double *>(dst), b.sp, (int)b.ncell);
+    else
+      hipLaunchKernelGGL((init_kernel<double, false>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
+                         static_cast<double *>(dst), b.sp, (int)b.ncell);
+  } else {
+    if (mrt)
+      hipLaunchKernelGGL((init_kernel<float, true>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
+                         static_cast<float *>(dst), b.sp, (int)b.ncell);
+    else
+      hipLaunchKernelGGL((init_kernel<float, false>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
+                         static_cast<float *>(dst), b.sp, (int)b.ncell);
+  }
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums) {
+  const int blocks = cell_blocks(b.ncell);
+  if (b.p.precision == DHIT_FP64)
+    hipLaunchKernelGGL((moments_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const double *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.partials);
+  else
+    hipLaunchKernelGGL((moments_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const float *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.partials);
+  DHIT_HIP(hipGetLastError());
+  launch_finalize_sums(b.stream, b.partials, blocks, d_sums);
+}
+
+void launch_velocity(dhit_box &b, const void *f, double *d_u) {
+  const int blocks = cell_blocks(b.ncell);
+  if (b.p.precision == DHIT_FP64)
+    hipLaunchKernelGGL((velocity_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const double *>(f), d_u, b.sp, (int)b.ncell);
+  else
+    hipLaunchKernelGGL((velocity_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const float *>(f), d_u, b.sp, (int)b.ncell);
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_pack(dhit_box &b, const void *f, double *d_out) {
+  const int64_t total = b.ncell * kQ;
+  const int blocks = (int)((total + kBlock - 1) / kBlock);
+  if (b.p.precision == DHIT_FP64)
+    hipLaunchKernelGGL((pack_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const double *>(f), d_out, b.stride, b.ncell);
+  else
+    hipLaunchKernelGGL((pack_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream,
+                       static_cast<const float *>(f), d_out, b.stride, b.ncell);
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_unpack(dhit_box &b, const double *d_in, void *f) {
+  const int64_t total = b.ncell * kQ;
+  const int blocks = (int)((total + kBlock - 1) / kBlock);
+  if (b.p.precision == DHIT_FP64)
+    hipLaunchKernelGGL((unpack_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream, d_in,
+                       static_cast<double *>(f), b.stride, b.ncell);
+  else
+    hipLaunchKernelGGL((unpack_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream, d_in,
+                       static_cast<float *>(f), b.stride, b.ncell);
+  DHIT_HIP(hipGetLastError());
+}
+
+}  // namespace dhit

@@ -1,0 +1,90 @@
+// Host-side runtime of the library: the box object and the launchers that
+// the C ABI (box.hip) calls.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/dhit.h"
+
+namespace dhit {
+
+// Error carrying an ABI status code; converted at the C boundary.
+struct Error : std::runtime_error {
+  int32_t code;
+  Error(int32_t c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define DHIT_HIP(expr)                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::dhit::Error(DHIT_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Parameters of the collision / update passed to kernels by value.
+struct StepParams {
+  int n;
+  int64_t stride;      // elements between consecutive population arrays
+  double rho0, inv_rho0;
+  // BGK-LBE: omega = 1/tau
+  double omega;
+  // MRT-LBE: r[k] = s_k / norm_k (0 for conserved rows), equilibrium constants
+  double r[19];
+  double w_eps, w_epsj, w_xx;
+  // DUGKS: tau, dt, h and the combination coefficients
+  double tau, dt, h;
+  double a_bp, b_bp;   // fbp = a_bp f~ + b_bp f^eq   (2tau-h)/(2tau+dt), 3h/(2tau+dt)
+  double alpha, beta;  // f_face = alpha fbar + beta f^eq   2tau/(2tau+h), h/(2tau+h)
+};
+
+constexpr int kHistoryCap = 4096;
+
+struct SpectrumWork;  // spectrum.hip
+
+}  // namespace dhit
+
+struct dhit_box {
+  dhit_params p{};
+  int n = 0;
+  int64_t ncell = 0;
+  int64_t stride = 0;        // padded per-population array length (elements)
+  size_t elem = 8;           // bytes per stored value
+  void *f[2] = {nullptr, nullptr};
+  bool own_f = false;
+  int cur = 0;               // f[cur] holds the state
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double *partials = nullptr;  // [5][max_blocks]
+  int max_blocks = 0;
+  double *hist = nullptr;      // [kHistoryCap][5]
+  int64_t steps = 0;
+  void *scratch = nullptr;     // DUGKS two-pass transform field
+  dhit::StepParams sp{};
+  dhit::SpectrumWork *spec = nullptr;
+};
+
+namespace dhit {
+
+// Launchers (each enqueues on b.stream; src/dst are population buffers).
+void launch_lbe_step(dhit_box &b, const void *src, void *dst, double *sums_out);
+void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out);
+void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst);
+void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
+void launch_pack(dhit_box &b, const void *f, double *d_out);     // state -> [19][ncell] double
+void launch_unpack(dhit_box &b, const double *d_in, void *f);    // [19][ncell] double -> state
+void launch_finalize_sums(hipStream_t s, const double *partials, int nblocks, double *out);
+void launch_velocity(dhit_box &b, const void *f, double *d_u);   // u = j / rho0, [3][ncell]
+
+// Spectrum (spectrum.hip)
+void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);
+void spectrum_free(dhit_box &b);
+
+// Number of blocks of a one-cell-per-thread launch over the box.
+inline int cell_blocks(int64_t ncell) { return (int)((ncell + 255) / 256); }
+
+}  // namespace dhit

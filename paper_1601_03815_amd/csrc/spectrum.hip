@@ -1,0 +1,197 @@
+// Energy spectrum and velocity-derivative statistics of a box (Sec. III):
+//   u = j/rho0 -> u_hat = DFT(u)/n^3 (hipFFT, real-to-complex, batch of 3)
+//   -> shell binning of 1/2 |u_hat|^2 and of |kappa|^2 1/2 |u_hat|^2
+//   -> spectral derivatives i kappa_a u_hat_a (inverse transforms)
+//   -> <(d_a u_a)^m>, m = 2, 3, 4 -> K, eps, S, F.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device_common.hpp"
+#include "runtime.hpp"
+
+namespace dhit {
+
+struct SpectrumWork {
+  int n = 0;
+  int nshell = 0;
+  int64_t nhalf = 0;  // modes of one real-to-complex transform, n*n*(n/2+1)
+  double *u = nullptr;
+  hipfftDoubleComplex *uh = nullptr;
+  hipfftDoubleComplex *tmp = nullptr;
+  double *shells = nullptr;    // [2][nshell]: E and kappa^2-weighted E
+  double *partials = nullptr;  // [5][blocks]
+  double *dstats = nullptr;    // [3][5]
+  hipfftHandle fwd = 0, inv = 0;
+  bool have_fwd = false, have_inv = false;
+};
+
+#define DHIT_FFT(expr)                                                                               \
+  do {                                                                                               \
+    hipfftResult r_ = (expr);                                                                        \
+    if (r_ != HIPFFT_SUCCESS) throw ::dhit::Error(DHIT_EDEVICE, std::string(#expr " failed, code ") + std::to_string((int)r_)); \
+  } while (0)
+
+// Signed integer wavenumber of FFT index i (numpy fftfreq order).
+__device__ __forceinline__ int signed_k(int i, int n) { return (i <= (n - 1) / 2) ? i : i - n; }
+
+// One thread per mode of the half spectrum; block histogram in LDS, then
+// one atomic add per shell and block.  Modes 0 < kx < n/2 stand for their
+// Hermitian partners too (weight 2).
+__global__ __launch_bounds__(256) void bin_kernel(const hipfftDoubleComplex *__restrict__ uh, int n, int64_t nhalf,
+                                                  int nshell, double inv_n6, double *__restrict__ shells) {
+  extern __shared__ double hist[];  // [2][nshell]
+  for (int i = threadIdx.x; i < 2 * nshell; i += blockDim.x) hist[i] = 0.0;
+  __syncthreads();
+  const int nxh = n / 2 + 1;
+  const double kfac = 2.0 * M_PI / n;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nhalf; m += (int64_t)gridDim.x * blockDim.x) {
+    const int kxh = (int)(m % nxh);
+    const int64_t r = m / nxh;
+    const int iy = (int)(r % n), iz = (int)(r / n);
+    const int kx = kxh, ky = signed_k(iy, n), kz = signed_k(iz, n);
+    double e = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const hipfftDoubleComplex v = uh[(int64_t)c * nhalf + m];
+      e += v.x * v.x + v.y * v.y;
+    }
+    const bool self = (kx == 0) || (2 * kx == n);
+    e *= 0.5 * inv_n6 * (self ? 1.0 : 2.0);
+    const int k2 = kx * kx + ky * ky + kz * kz;
+    const int s = (int)rint(sqrt((double)k2));
+    atomicAdd(&hist[s], e);
+    atomicAdd(&hist[nshell + s], kfac * kfac * (double)k2 * e);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * nshell; i += blockDim.x)
+    if (hist[i] != 0.0) atomicAdd(&shells[i], hist[i]);
+}
+
+// tmp = i kappa_a u_hat_a on the half spectrum; the Nyquist wavenumber of
+// the derivative direction is set to zero.
+__global__ __launch_bounds__(256) void deriv_kernel(const hipfftDoubleComplex *__restrict__ uha,
+                                                    hipfftDoubleComplex *__restrict__ out, int n, int64_t nhalf,
+                                                    int axis) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nhalf) return;
+  const int nxh = n / 2 + 1;
+  const int kxh = (int)(m % nxh);
+  const int64_t r = m / nxh;
+  const int iy = (int)(r % n), iz = (int)(r / n);
+  int k = axis == 0 ? kxh : (axis == 1 ? signed_k(iy, n) : signed_k(iz, n));
+  if ((n % 2 == 0) && (2 * k == n || 2 * k == -n)) k = 0;
+  const double kap = 2.0 * M_PI / n * k;
+  const hipfftDoubleComplex v = uha[m];
+  hipfftDoubleComplex o;
+  o.x = -kap * v.y;
+  o.y = kap * v.x;
+  out[m] = o;
+}
+
+// Sums of d^2, d^3, d^4 of a real field scaled by `scale`.
+__global__ __launch_bounds__(kBlock) void power_sums_kernel(const double *__restrict__ d, int64_t ncell, double scale,
+                                                            double *__restrict__ partials) {
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ncell; i += (int64_t)gridDim.x * kBlock) {
+    const double x = d[i] * scale;
+    const double x2 = x * x;
+    v[0] += x2;
+    v[1] += x2 * x;
+    v[2] += x2 * x2;
+  }
+  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+}
+
+static void ensure_work(dhit_box &b) {
+  if (b.spec) return;
+  SpectrumWork *w = new SpectrumWork();
+  b.spec = w;
+  const int n = b.n;
+  w->n = n;
+  w->nhalf = (int64_t)n * n * (n / 2 + 1);
+  w->nshell = (int)std::floor(std::sqrt(3.0) * (n / 2 + 1)) + 2;
+  if (hipMalloc(&w->u, 3 * b.ncell * sizeof(double)) != hipSuccess ||
+      hipMalloc(&w->uh, 3 * w->nhalf * sizeof(hipfftDoubleComplex)) != hipSuccess ||
+      hipMalloc(&w->tmp, w->nhalf * sizeof(hipfftDoubleComplex)) != hipSuccess ||
+      hipMalloc(&w->shells, 2 * w->nshell * sizeof(double)) != hipSuccess ||
+      hipMalloc(&w->partials, 5 * 1024 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&w->dstats, 3 * 5 * sizeof(double)) != hipSuccess)
+    throw Error(DHIT_ENOMEM, "cannot allocate spectrum work space");
+  int dims[3] = {n, n, n};
+  DHIT_FFT(hipfftPlanMany(&w->fwd, 3, dims, nullptr, 1, (int)b.ncell, nullptr, 1, (int)w->nhalf, HIPFFT_D2Z, 3));
+  w->have_fwd = true;
+  DHIT_FFT(hipfftPlanMany(&w->inv, 3, dims, nullptr, 1, (int)w->nhalf, nullptr, 1, (int)b.ncell, HIPFFT_Z2D, 1));
+  w->have_inv = true;
+}
+
+void spectrum_free(dhit_box &b) {
+  SpectrumWork *w = b.spec;
+  if (!w) return;
+  if (w->have_fwd) hipfftDestroy(w->fwd);
+  if (w->have_inv) hipfftDestroy(w->inv);
+  if (w->u) (void)hipFree(w->u);
+  if (w->uh) (void)hipFree(w->uh);
+  if (w->tmp) (void)hipFree(w->tmp);
+  if (w->shells) (void)hipFree(w->shells);
+  if (w->partials) (void)hipFree(w->partials);
+  if (w->dstats) (void)hipFree(w->dstats);
+  delete w;
+  b.spec = nullptr;
+}
+
+void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host) {
+  ensure_work(b);
+  SpectrumWork &w = *b.spec;
+  const int n = b.n;
+  DHIT_FFT(hipfftSetStream(w.fwd, b.stream));
+  DHIT_FFT(hipfftSetStream(w.inv, b.stream));
+  launch_velocity(b, b.f[b.cur], w.u);
+  DHIT_FFT(hipfftExecD2Z(w.fwd, w.u, w.uh));
+  DHIT_HIP(hipMemsetAsync(w.shells, 0, 2 * w.nshell * sizeof(double), b.stream));
+  const double inv_n3 = 1.0 / ((double)n * n * n);
+  {
+    const int blocks = (int)std::min<int64_t>((w.nhalf + 255) / 256, 2048);
+    hipLaunchKernelGGL(bin_kernel, dim3(blocks), dim3(256), 2 * w.nshell * sizeof(double), b.stream, w.uh, n,
+                       w.nhalf, w.nshell, inv_n3 * inv_n3, w.shells);
+    DHIT_HIP(hipGetLastError());
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int blocks = (int)((w.nhalf + 255) / 256);
+    hipLaunchKernelGGL(deriv_kernel, dim3(blocks), dim3(256), 0, b.stream, w.uh + a * w.nhalf, w.tmp, n, w.nhalf, a);
+    DHIT_HIP(hipGetLastError());
+    DHIT_FFT(hipfftExecZ2D(w.inv, w.tmp, w.u));  // overwrites u[0 .. ncell)
+    const int rb = (int)std::min<int64_t>((b.ncell + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(power_sums_kernel, dim3(rb), dim3(kBlock), 0, b.stream, w.u, b.ncell, inv_n3, w.partials);
+    DHIT_HIP(hipGetLastError());
+    launch_finalize_sums(b.stream, w.partials, rb, w.dstats + 5 * a);
+  }
+  std::vector<double> sh(2 * w.nshell);
+  double ds[15];
+  DHIT_HIP(hipMemcpyAsync(sh.data(), w.shells, sh.size() * sizeof(double), hipMemcpyDeviceToHost, b.stream));
+  DHIT_HIP(hipMemcpyAsync(ds, w.dstats, sizeof(ds), hipMemcpyDeviceToHost, b.stream));
+  DHIT_HIP(hipStreamSynchronize(b.stream));
+  for (int k = 0; k <= kmax; ++k) E_host[k] = k < w.nshell ? sh[k] : 0.0;
+  if (stats_host) {
+    double K = 0, D = 0;
+    for (int k = 0; k < w.nshell; ++k) {
+      K += sh[k];
+      D += sh[w.nshell + k];
+    }
+    double num3 = 0, den3 = 0, num4 = 0, den4 = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double m2 = ds[5 * a + 0] * inv_n3, m3 = ds[5 * a + 1] * inv_n3, m4 = ds[5 * a + 2] * inv_n3;
+      num3 += m3;
+      num4 += m4;
+      den3 += std::pow(m2, 1.5);
+      den4 += m2 * m2;
+    }
+    stats_host[0] = K;
+    stats_host[1] = 2.0 * b.p.nu * D;
+    stats_host[2] = den3 > 0 ? num3 / den3 : 0.0;
+    stats_host[3] = den4 > 0 ? num4 / den4 : 0.0;
+  }
+  for (int i = 0; i < 15; ++i)
+    if (!std::isfinite(ds[i])) throw Error(DHIT_ENONFINITE, "velocity field is not finite");
+}
+
+}  // namespace dhit

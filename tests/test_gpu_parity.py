@@ -1,0 +1,282 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances
+  FP64: every element within 1e-12 of the oracle, relative to the largest
+        magnitude of the compared field (the bar set for the FP64 path).
+  FP32: every element within 2e-6 relative to the largest magnitude after
+        one step (float rounding of ~100 operations on values of one
+        magnitude: a few tens of units in the last place, 2^-24 = 6e-8).
+
+LBE boxes store post-collision populations, so the GPU result of a step from
+a post-collision field P is compared with collide(stream(P)) of the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1601_03815_amd as dhit
+import synth
+
+pytestmark = pytest.mark.gpu
+
+Q = 19
+TOL64 = 1e-12
+TOL32 = 2e-6
+
+
+def rel_err(got, ref):
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def oracle_one_step(f, method, nu, dt=0.5):
+    if method == "dugks":
+        return O.dugks_step(f, nu=nu, dt=dt)
+    return O.collide(O.stream(f), method, nu)
+
+
+METHOD_VARIANTS = [("bgk", {}), ("mrt", {}), ("dugks", {}), ("dugks", {"variant": dhit.VARIANT_TWO_PASS})]
+
+
+def _vid(mv):
+    m, o = mv
+    return m + ("-twopass" if o else "")
+
+
+@pytest.mark.parametrize("mv", METHOD_VARIANTS, ids=_vid)
+@pytest.mark.parametrize("n", [4, 5, 8, 12, 17, 32])
+def test_one_step_fp64_random_state(mv, n):
+    """One step from an arbitrary non-equilibrium state: grids from the
+    minimum size through odd and ragged sizes (n^3 not a multiple of the
+    256-cell block) to several tiles."""
+    method, over = mv
+    nu = 0.01
+    f0 = synth.random_populations(n, seed=1000 + n, amplitude=0.01)
+    with dhit.Box(n, method, "fp64", nu, **over) as box:
+        box.set_populations(f0)
+        box.step(1)
+        got = box.get_populations()
+        _, _, sums = box.moments(want_fields=False)
+        hist = box.sums_history(1)[0]
+    ref = oracle_one_step(f0, method, nu)
+    assert rel_err(got, ref) <= TOL64
+    ref_sums = O.moments(ref)[2]
+    scale = np.abs(f0).sum()
+    assert np.abs(sums - ref_sums).max() <= TOL64 * scale
+    assert np.abs(hist - ref_sums).max() <= TOL64 * scale
+
+
+@pytest.mark.parametrize("mv", METHOD_VARIANTS, ids=_vid)
+@pytest.mark.parametrize("n", [5, 16])
+def test_one_step_fp32_random_state(mv, n):
+    method, over = mv
+    nu = 0.01
+    f0 = synth.random_populations(n, seed=2000 + n, amplitude=0.01)
+    f0 = f0.astype(np.float32).astype(np.float64)   # representable start state
+    with dhit.Box(n, method, "fp32", nu, **over) as box:
+        box.set_populations(f0)
+        box.step(1)
+        got = box.get_populations()
+    ref = oracle_one_step(f0, method, nu)
+    assert rel_err(got, ref) <= TOL32
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+def test_non_default_parameters(method):
+    """Other viscosity, rho0, DUGKS time step and MRT rates go through."""
+    n, nu = 6, 0.037
+    over = dict(rho0=1.3)
+    mrt = None
+    if method == "dugks":
+        over["dt"] = 0.35
+    if method == "mrt":
+        over.update(s1=1.5, s2=1.1, s4=1.3, s10=1.2, s16=1.7, w_eps=3.0, w_epsj=-5.5, w_xx=-0.5)
+    f0 = synth.random_populations(n, seed=77, amplitude=0.02)
+    with dhit.Box(n, method, "fp64", nu, **over) as box:
+        box.set_populations(f0)
+        box.step(1)
+        got = box.get_populations()
+    if method == "dugks":
+        ref = O.dugks_step(f0, nu=nu, dt=0.35, rho0=1.3)
+    else:
+        if method == "mrt":
+            s = O.mrt_rates(nu, s1=1.5, s2=1.1, s4=1.3, s10=1.2, s16=1.7)
+            mrt = dict(s=s, w_eps=3.0, w_epsj=-5.5, w_xx=-0.5)
+        ref = O.collide(O.stream(f0), method, nu, rho0=1.3, mrt=mrt)
+    assert rel_err(got, ref) <= TOL64
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_init_velocity_field(method, precision):
+    n = 8
+    u = synth.dhit_field(n, seed=3, k0=2, u_rms=0.05)
+    drho = synth.random_populations(1, seed=4)[0, 0, 0, 0] + 0.001 * np.sin(np.arange(n ** 3)).reshape(n, n, n)
+    with dhit.Box(n, method, precision, 0.01) as box:
+        box.init_velocity_field(u, drho)
+        got = box.get_populations()
+        d, j, _ = box.moments()
+    if method == "mrt":
+        ref = O.init_mrt_equilibrium(u, drho)
+    else:
+        ref = O.init_equilibrium(u, drho)
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert rel_err(got, ref) <= tol
+    assert rel_err(j, u) <= tol
+    assert rel_err(d, drho) <= tol
+
+
+def test_taylor_green_config_fp64():
+    """Taylor-Green vortex, 32^3, U0 = 0.05, nu = 0.01: 200 BGK-LBE and
+    MRT-LBE steps and 100 DUGKS steps; populations after the run and the
+    global sums reduced at the end of every step against the oracle's."""
+    n, nu = 32, 0.01
+    u = synth.taylor_green(n, 0.05)
+    for method, steps in (("bgk", 200), ("mrt", 200), ("dugks", 100)):
+        with dhit.Box(n, method, "fp64", nu) as box:
+            box.init_velocity_field(u)
+            box.step(steps)
+            got = box.get_populations()
+            hist = box.sums_history(steps)
+        if method == "dugks":
+            cur = O.init_equilibrium(u)
+        elif method == "mrt":
+            cur = O.init_mrt_equilibrium(u)
+        else:
+            cur = O.init_equilibrium(u)
+        ref_hist = []
+        for _ in range(steps):
+            if method == "dugks":
+                cur = O.dugks_step(cur, nu=nu)
+            else:
+                cur = O.lbe_step(cur, method, nu)
+            ref_hist.append(O.moments(cur)[2])
+        ref_hist = np.array(ref_hist)
+        ref = cur if method == "dugks" else O.collide(cur, method, nu)
+        assert rel_err(got, ref) <= TOL64, method
+        np.testing.assert_allclose(hist[:, 4], ref_hist[:, 4], rtol=TOL64, atol=0)
+        scale = np.abs(got).sum()
+        assert np.abs(hist[:, :4] - ref_hist[:, :4]).max() <= TOL64 * scale
+
+
+@pytest.mark.parametrize("n", [5, 16, 32])
+def test_energy_spectrum_parity(n):
+    nu = 0.005
+    u = synth.dhit_field(n, seed=9, k0=4 if n >= 16 else 2, u_rms=0.05)
+    kmax = int(np.ceil(np.sqrt(3) * (n // 2))) + 1
+    with dhit.Box(n, "bgk", "fp64", nu) as box:
+        box.init_velocity_field(u)
+        E, st = box.energy_spectrum(kmax)
+    E_ref, st_ref = O.energy_spectrum(u, nu, kmax)
+    assert np.abs(E - E_ref).max() <= TOL64 * E_ref.max()
+    for k in ("K", "eps"):
+        assert abs(st[k] / st_ref[k] - 1) <= TOL64, k
+    for k in ("S", "F"):
+        assert abs(st[k] - st_ref[k]) <= 1e-10 * max(1.0, abs(st_ref[k])), k
+
+
+def test_energy_spectrum_taylor_green_closed_form():
+    n, u0, nu = 32, 0.05, 0.01
+    with dhit.Box(n, "dugks", "fp64", nu) as box:
+        box.init_velocity_field(synth.taylor_green(n, u0))
+        E, st = box.energy_spectrum(n // 2)
+    assert abs(st["K"] / (u0 ** 2 / 8) - 1) < 1e-13
+    assert abs(E[2] / (u0 ** 2 / 8) - 1) < 1e-13
+    assert abs(st["F"] - 27 / 8) < 1e-10 and abs(st["S"]) < 1e-10
+
+
+def _sample_cells(n, count, seed):
+    """Random cells plus every corner and the middle of every face and edge
+    (where the periodic wrap is exercised)."""
+    rng = np.random.default_rng(seed)
+    pts = set(int(c) for c in rng.integers(0, n ** 3, count))
+    for z in (0, n // 2, n - 1):
+        for y in (0, n // 2, n - 1):
+            for x in (0, n // 2, n - 1):
+                pts.add((z * n + y) * n + x)
+    return np.array(sorted(pts), dtype=np.int64)
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+@pytest.mark.parametrize("n", [128, 256])
+def test_full_size_sampled_cells_fp64(method, n):
+    """Full-size boxes (the DHIT and benchmark sizes), in the launch
+    configuration the benchmark times: one step from a random state, checked
+    on sampled cells that the oracle computes one by one."""
+    nu = 0.005 if n == 128 else 0.0025
+    print("full-size sampled: %s n=%d" % (method, n), flush=True)
+    f0 = synth.random_populations(n, seed=5 + n, amplitude=0.01)
+    with dhit.Box(n, method, "fp64", nu) as box:
+        box.set_populations(f0)
+        box.step(1)
+        got = box.get_populations().reshape(Q, -1)
+    cells = _sample_cells(n, 3000, seed=n)
+    if method == "dugks":
+        ref = O.dugks_cells(f0, cells, nu=nu)
+    else:
+        ref = O.lbe_pull_cells(f0, cells, method, nu)
+    assert rel_err(got[:, cells].T, ref) <= TOL64
+
+
+def test_step_method_mismatch_and_validation():
+    with dhit.Box(4, "dugks", "fp64", 0.01) as box:
+        with pytest.raises(dhit.DhitError) as e:
+            dhit.step_lbe(box.handle, 1)
+        assert e.value.code == -4
+    with dhit.Box(4, "bgk", "fp64", 0.01) as box:
+        with pytest.raises(dhit.DhitError) as e:
+            dhit.step_dugks(box.handle, 1)
+        assert e.value.code == -4
+        with pytest.raises(dhit.DhitError):
+            box.sums_history(1)   # no steps yet
+
+
+def test_nonfinite_is_reported():
+    n = 6
+    f0 = synth.random_populations(n, seed=1)
+    f0[3, 1, 2, 3] = np.nan
+    with dhit.Box(n, "bgk", "fp64", 0.01) as box:
+        box.set_populations(f0)
+        box.step(2)
+        with pytest.raises(dhit.NonFiniteError):
+            box.synchronize()
+        with pytest.raises(dhit.NonFiniteError):
+            box.moments()
+
+
+def test_torch_buffers_and_view():
+    import torch
+    n = 8
+    u = synth.taylor_green(n, 0.05)
+    with dhit.Box(n, "bgk", "fp64", 0.01) as box:
+        box.init_velocity_field(u)
+        box.step(3)
+        torch.cuda.synchronize()
+        view = box.populations_tensor().cpu().numpy()
+        np.testing.assert_array_equal(view.reshape(Q, n, n, n), box.get_populations())
+    with dhit.Box(n, "bgk", "fp64", 0.01, torch_memory=False) as box:
+        box.init_velocity_field(u)
+        box.step(3)
+        np.testing.assert_array_equal(box.get_populations(), view.reshape(Q, n, n, n))
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+def test_batch_equals_single_boxes(method):
+    sizes = [8, 12, 5, 16]
+    states = [synth.random_populations(n, seed=40 + i) for i, n in enumerate(sizes)]
+    singles = []
+    for n, f in zip(sizes, states):
+        with dhit.Box(n, method, "fp32", 0.01) as b:
+            b.set_populations(f)
+            b.step(3)
+            singles.append(b.get_populations())
+    boxes = [dhit.Box(n, method, "fp32", 0.01) for n in sizes]
+    try:
+        for b, f in zip(boxes, states):
+            b.set_populations(f)
+        dhit.step_boxes(boxes, 3)
+        for b, ref in zip(boxes, singles):
+            np.testing.assert_array_equal(b.get_populations(), ref)
+            assert b.steps == 3
+    finally:
+        for b in boxes:
+            b.close()
