@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput of the LBE and DUGKS time steps on one MI355X.
+
+Workload: decaying isotropic turbulence on a 256^3 periodic box (random
+solenoidal field, E(k) ~ k^4 exp(-2k^2/k0^2), k0 = 4, u' = 0.05, seed 1,
+nu = 0.0025), one MRT-LBE box and one DUGKS box (dt = 0.5), FP64.  One
+timed step = one MRT-LBE step + one DUGKS step, each with its per-step FP64
+global reduction (the whole hot path; inputs already resident in HBM).
+
+value = 2 * n^3 * steps / seconds / 1e6  (MLUPS, cell updates of both methods)
+
+Also measured and reported on the same JSON line:
+  * per-method MLUPS in FP64 and FP32 (the deviation-form precision path),
+  * `roofline` for the kernel with the largest share of the timed region:
+    algorithmic bytes per launch (19 reads + 19 writes of the population
+    state per cell) over its mean launch time from HIP events recorded on
+    the box's stream around every launch in the timed region;
+  * `traffic`: HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE
+    counters (committed under profiles/), when they were taken on the
+    current kernel source;
+  * `cpu_baseline`: the FP64 CPU oracle timed on this host (rank 0, N = 1).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+BYTES_PER_CELL = {"fp64": 38 * 8, "fp32": 38 * 4}   # 19 reads + 19 writes per cell update
+
+
+def kernel_source_hash(kernel):
+    """Hash of the source files a kernel is built from (to decide whether
+    stored counter readings still describe it)."""
+    csrc = os.path.join(ROOT, "paper_1601_03815_amd", "csrc")
+    files = {"lbe": ["lbe.hip", "collision.hpp", "device_common.hpp", "lattice.hpp"],
+             "dugks_face": ["dugks.hip", "device_common.hpp", "lattice.hpp"],
+             "dugks_transform": ["dugks.hip", "device_common.hpp", "lattice.hpp"],
+             "dugks_fused": ["dugks_fused.hip", "device_common.hpp", "lattice.hpp"]}.get(kernel, [])
+    h = hashlib.sha256()
+    for f in files:
+        p = os.path.join(csrc, f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, precision, n):
+    """HBM bytes per launch measured with rocprofv3 counters, if recorded for
+    the current source of this kernel (profiles/traffic.json)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get("%s/%s/%d" % (kernel, precision, n))
+    except ValueError:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(boxes, steps, torch):
+    """Run `steps` rounds of one step on every box (all on one stream);
+    returns elapsed ms from HIP events on that stream."""
+    stream = boxes[0].stream
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    for b in boxes:
+        b.synchronize()
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        for b in boxes:
+            b.step(1)
+    stop.record(stream)
+    stop.synchronize()
+    for b in boxes:
+        b.synchronize()
+    return start.elapsed_time(stop)
+
+
+def cpu_baseline(n, nu, u256):
+    """The FP64 CPU oracle on a bounded sample of the workload: one MRT-LBE
+    step of the full n^3 field and one DUGKS step of a 128^3 field of the same
+    recipe (the oracle's DUGKS cost per cell does not depend on the box
+    size).  Returns the combined rate defined like `value`."""
+    import oracle
+    import synth
+    f = oracle.init_mrt_equilibrium(u256)
+    t0 = time.perf_counter()
+    oracle.lbe_step(f, "mrt", nu)
+    t_lbe = time.perf_counter() - t0
+    del f
+    m = min(n, 128)
+    g = oracle.init_equilibrium(synth.dhit_field(m, seed=1, k0=4, u_rms=0.05))
+    t0 = time.perf_counter()
+    oracle.dugks_step(g, nu=nu)
+    t_dugks = time.perf_counter() - t0
+    r_lbe = n ** 3 / t_lbe / 1e6
+    r_dugks = m ** 3 / t_dugks / 1e6
+    value = 2.0 / (1.0 / r_lbe + 1.0 / r_dugks)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(value, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "MRT-LBE: 1 oracle step of the %d^3 field (%.2f s, %.3f MLUPS); DUGKS: 1 oracle step "
+                      "of a %d^3 field of the same recipe (%.2f s, %.4f MLUPS); value = 2/(1/r_lbe + 1/r_dugks)"
+                      % (n, t_lbe, r_lbe, m, t_dugks, r_dugks),
+            "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--nu", type=float, default=0.0025)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the per-step update of one box is not "
+              "sharded (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1601_03815_amd as dhit
+    import synth
+
+    n, nu, K, W = args.n, args.nu, args.steps, args.warmup
+    print("bench: building the %d^3 DHIT field" % n, file=sys.stderr, flush=True)
+    u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
+    stream = torch.cuda.Stream()
+
+    def make(method, precision):
+        b = dhit.Box(n, method, precision, nu, stream=stream)
+        b.init_velocity_field(u)
+        return b
+
+    results = {}
+    per_kernel = {}
+    legs = [("fp64",)] + ([] if args.no_fp32 else [("fp32",)])
+    main_ms = None
+    for (precision,) in legs:
+        print("bench: %s leg" % precision, file=sys.stderr, flush=True)
+        lbe, dug = make("mrt", precision), make("dugks", precision)
+        time_steps([lbe, dug], W, torch)                       # warm-up
+        for b in (lbe, dug):
+            dhit.set_kernel_timing(b.handle, True)
+        ms = time_steps([lbe, dug], K, torch)                  # timed region
+        kt = {}
+        for b in (lbe, dug):
+            for name, (t, c) in dhit.read_kernel_timings(b.handle).items():
+                if c:
+                    kt[name] = (kt.get(name, (0.0, 0))[0] + t, kt.get(name, (0.0, 0))[1] + c)
+            dhit.set_kernel_timing(b.handle, False)
+        # per-method rates (separate timed loops, same stream)
+        ms_lbe = time_steps([lbe], K, torch)
+        ms_dug = time_steps([dug], K, torch)
+        _, _, s_lbe = lbe.moments(want_fields=False)
+        _, _, s_dug = dug.moments(want_fields=False)
+        results[precision] = {
+            "ms_per_step": ms / K,
+            "mlups": 2 * n ** 3 * K / (ms * 1e-3) / 1e6,
+            "mlups_lbe_mrt": n ** 3 * K / (ms_lbe * 1e-3) / 1e6,
+            "mlups_dugks": n ** 3 * K / (ms_dug * 1e-3) / 1e6,
+            "K_lbe": s_lbe[4] / n ** 3, "K_dugks": s_dug[4] / n ** 3,
+        }
+        per_kernel[precision] = kt
+        if precision == "fp64":
+            main_ms = ms
+        lbe.close()
+        dug.close()
+        torch.cuda.empty_cache()
+
+    # achievable-bandwidth reference: the library's plain copy kernel
+    nbytes = 1 << 31
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    c = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        dhit.device_copy(c.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    ev0.record(stream)
+    for _ in range(10):
+        dhit.device_copy(c.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    copy_gbs = 2 * nbytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del a, c
+    torch.cuda.empty_cache()
+
+    # dominant kernel of the FP64 timed region
+    kt = per_kernel["fp64"]
+    dom = max(kt, key=lambda k: kt[k][0])
+    t_ms, launches = kt[dom]
+    mean_s = t_ms / launches * 1e-3
+    alg_bytes = BYTES_PER_CELL["fp64"] * n ** 3
+    achieved = alg_bytes / mean_s / 1e9
+    traffic = stored_traffic(dom, "fp64", n)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "mean_launch_ms": round(mean_s * 1e3, 4),
+                "algorithmic_bytes_per_launch": alg_bytes}
+    kernels = {}
+    for prec, d in per_kernel.items():
+        for name, (t, c) in d.items():
+            mean = t / c * 1e-3
+            eff = (BYTES_PER_CELL[prec] * n ** 3 / mean / 1e9) if name != "finalize" else None
+            kernels["%s/%s" % (prec, name)] = {"mean_ms": round(mean * 1e3, 4), "launches": c,
+                                                "share": round(t / sum(v[0] for v in d.values()), 4),
+                                                "eff_GBs": None if eff is None else round(eff, 1)}
+
+    fp64 = results["fp64"]
+    line = {
+        "metric": "MLUPS (LBE & DUGKS, 256^3) + % HBM roofline; FP32 vs FP64 at stated error",
+        "value": round(fp64["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(main_ms / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dhit-%d^3-mrt-lbe+dugks-fp64" % n, "n": n, "nu": nu, "k0": 4,
+                   "u_rms": 0.05, "seed": 1, "lbe_collision": "mrt", "dugks_dt": 0.5,
+                   "step": "1 MRT-LBE step + 1 DUGKS step, each with its FP64 global reduction"},
+        "roofline": roofline,
+        "mlups_fp64": {"lbe_mrt": round(fp64["mlups_lbe_mrt"], 1), "dugks": round(fp64["mlups_dugks"], 1),
+                       "dugks_per_lbe_time_unit": round(fp64["mlups_dugks"] / 2, 1)},
+        "kernels": kernels,
+        "hbm_copy_GBs": round(copy_gbs, 1),
+    }
+    if "fp32" in results:
+        r = results["fp32"]
+        line["mlups_fp32"] = {"combined": round(r["mlups"], 1), "lbe_mrt": round(r["mlups_lbe_mrt"], 1),
+                              "dugks": round(r["mlups_dugks"], 1),
+                              "speedup_vs_fp64": round(r["mlups"] / fp64["mlups"], 3)}
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(n, nu, u)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

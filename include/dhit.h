@@ -187,6 +187,32 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * streams are made to wait for it.  Results equal per-box steps. */
 int32_t step_batch(dhit_box **boxes, int32_t nbox, int32_t nsteps);
 
+/* Kernel kinds reported by read_kernel_timings. */
+enum dhit_kernel {
+    DHIT_K_LBE = 0,              /* LBE pull streaming + collision */
+    DHIT_K_DUGKS_TRANSFORM = 1,  /* DUGKS cell transform (two-pass variant) */
+    DHIT_K_DUGKS_FACE = 2,       /* DUGKS face fluxes and update (two-pass variant) */
+    DHIT_K_DUGKS_FUSED = 3,      /* DUGKS single-kernel step */
+    DHIT_K_FINALIZE = 4,         /* global-sum finalisation */
+    DHIT_NKERNEL = 5
+};
+
+/* Per-kernel timing.  While enabled, every kernel the box launches is
+ * bracketed by two HIP events recorded on the box's stream (at most 8192
+ * launches are kept; older ones are dropped).  read_kernel_timings waits for
+ * the stream, adds the elapsed time of every recorded launch to ms[kind]
+ * (milliseconds) and the launch count to launches[kind] (both arrays of
+ * DHIT_NKERNEL entries, overwritten), and clears the record.  Enabling or
+ * disabling also clears it. */
+int32_t set_kernel_timing(dhit_box *b, int32_t enable);
+int32_t read_kernel_timings(dhit_box *b, double *ms, int64_t *launches);
+
+/* Copy `bytes` bytes (a multiple of 16) between two 16-byte-aligned
+ * device buffers on `stream` (a hipStream_t, NULL = the null stream) with a
+ * plain streaming copy kernel: the reference for achievable HBM bandwidth
+ * and for calibrating hardware byte counters.  Asynchronous. */
+int32_t device_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *dhit_last_error(void);
 

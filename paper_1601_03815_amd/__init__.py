@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, last_error,
     moments, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
-    sums_history,
+    sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
 )
 from . import _binding
 

@@ -90,6 +90,9 @@ def _load():
         "box_synchronize": ([box], i32),
         "current_populations": ([box, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64)], i32),
         "step_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32], i32),
+        "set_kernel_timing": ([box, i32], i32),
+        "read_kernel_timings": ([box, dp, dp], i32),
+        "device_copy": ([ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p], i32),
         "dhit_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -229,9 +232,29 @@ def step_batch(handles, nsteps=1):
     _check(_lib.step_batch(arr, len(handles), int(nsteps)))
 
 
+KERNEL_NAMES = ["lbe", "dugks_transform", "dugks_face", "dugks_fused", "finalize"]
+
+
+def set_kernel_timing(h, enable=True):
+    _check(_lib.set_kernel_timing(h, 1 if enable else 0))
+
+
+def read_kernel_timings(h):
+    """{kernel name: (total ms, launches)} since the last read."""
+    ms = np.zeros(len(KERNEL_NAMES))
+    cnt = np.zeros(len(KERNEL_NAMES), dtype=np.int64)
+    _check(_lib.read_kernel_timings(h, _ptr(ms), _ptr(cnt)))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
+def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
+    _check(_lib.device_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nbytes),
+                            ctypes.c_void_p(stream_handle)))
+
+
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
     "init_velocity_field", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
-    "step_batch", "dhit_last_error",
+    "step_batch", "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",
 ]

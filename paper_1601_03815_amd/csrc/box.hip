@@ -229,6 +229,7 @@ int32_t destroy_box(dhit_box *b) {
   if (!b) return DHIT_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   dhit::spectrum_free(*b);
+  dhit::timer_free(*b);
   if (b->own_f) {
     if (b->f[0]) (void)hipFree(b->f[0]);
     if (b->f[1]) (void)hipFree(b->f[1]);

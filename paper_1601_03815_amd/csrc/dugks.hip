@@ -133,13 +133,21 @@ static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums
   const Real *s = static_cast<const Real *>(src);
   Real *d = static_cast<Real *>(dst);
   Real *bp = static_cast<Real *>(b.scratch);
-  hipLaunchKernelGGL((dugks_transform_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, b.sp,
-                     (int)b.ncell);
-  DHIT_HIP(hipGetLastError());
-  hipLaunchKernelGGL((dugks_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
-                     (int)b.ncell, b.partials);
-  DHIT_HIP(hipGetLastError());
-  launch_finalize_sums(b.stream, b.partials, blocks, sums_out);
+  {
+    TimedLaunch t(b, DHIT_K_DUGKS_TRANSFORM);
+    hipLaunchKernelGGL((dugks_transform_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, b.sp,
+                       (int)b.ncell);
+    DHIT_HIP(hipGetLastError());
+    t.done();
+  }
+  {
+    TimedLaunch t(b, DHIT_K_DUGKS_FACE);
+    hipLaunchKernelGGL((dugks_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
+                       (int)b.ncell, b.partials);
+    DHIT_HIP(hipGetLastError());
+    t.done();
+  }
+  launch_finalize_sums(b, b.partials, blocks, sums_out);
 }
 
 void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out) {

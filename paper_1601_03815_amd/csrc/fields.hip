@@ -93,9 +93,11 @@ __global__ __launch_bounds__(1024) void finalize_sums_kernel(const double *__res
   }
 }
 
-void launch_finalize_sums(hipStream_t s, const double *partials, int nblocks, double *out) {
-  hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, s, partials, nblocks, out);
+void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out) {
+  TimedLaunch t(b, DHIT_K_FINALIZE);
+  hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, b.stream, partials, nblocks, out);
   DHIT_HIP(hipGetLastError());
+  t.done();
 }
 
 void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst) {
@@ -128,7 +130,7 @@ void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, dou
     hipLaunchKernelGGL((moments_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream,
                        static_cast<const float *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.partials);
   DHIT_HIP(hipGetLastError());
-  launch_finalize_sums(b.stream, b.partials, blocks, d_sums);
+  launch_finalize_sums(b, b.partials, blocks, d_sums);
 }
 
 void launch_velocity(dhit_box &b, const void *f, double *d_u) {
@@ -166,4 +168,24 @@ void launch_unpack(dhit_box &b, const double *d_in, void *f) {
   DHIT_HIP(hipGetLastError());
 }
 
+// Plain streaming copy, 16 bytes per thread and iteration.
+__global__ __launch_bounds__(kBlock) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                      int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
 }  // namespace dhit
+
+extern "C" int32_t device_copy(void *dst, const void *src, int64_t bytes, void *stream) {
+  (void)hipGetLastError();
+  if (!dst || !src || bytes < 0 || (bytes & 15) || ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15))
+    return DHIT_EINVAL;
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return DHIT_OK;
+  const int64_t want = (n16 + dhit::kBlock - 1) / dhit::kBlock;
+  const int blocks = (int)(want < 256 * 64 ? want : 256 * 64);
+  hipLaunchKernelGGL(dhit::copy_kernel, dim3(blocks), dim3(dhit::kBlock), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  return hipGetLastError() == hipSuccess ? DHIT_OK : DHIT_EDEVICE;
+}

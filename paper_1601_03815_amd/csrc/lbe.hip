@@ -54,6 +54,7 @@ static void lbe_step_typed(dhit_box &b, const void *src, void *dst, double *sums
   const int blocks = cell_blocks(b.ncell);
   const Real *s = static_cast<const Real *>(src);
   Real *d = static_cast<Real *>(dst);
+  TimedLaunch t(b, DHIT_K_LBE);
   if (b.p.method == DHIT_LBE_BGK)
     hipLaunchKernelGGL((lbe_pull_kernel<kBGK, Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, d, b.sp,
                        (int)b.ncell, b.partials);
@@ -61,7 +62,8 @@ static void lbe_step_typed(dhit_box &b, const void *src, void *dst, double *sums
     hipLaunchKernelGGL((lbe_pull_kernel<kMRT, Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, d, b.sp,
                        (int)b.ncell, b.partials);
   DHIT_HIP(hipGetLastError());
-  launch_finalize_sums(b.stream, b.partials, blocks, sums_out);
+  t.done();
+  launch_finalize_sums(b, b.partials, blocks, sums_out);
 }
 
 void launch_lbe_step(dhit_box &b, const void *src, void *dst, double *sums_out) {

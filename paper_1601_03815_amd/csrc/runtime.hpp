@@ -46,6 +46,16 @@ constexpr int kHistoryCap = 4096;
 
 struct SpectrumWork;  // spectrum.hip
 
+// Ring of event pairs bracketing kernel launches (see set_kernel_timing).
+struct KernelTimer {
+  static constexpr int kCap = 8192;
+  bool enabled = false;
+  hipEvent_t start[kCap] = {}, stop[kCap] = {};
+  int kind[kCap] = {};
+  bool created = false;
+  int64_t count = 0;  // launches recorded since the last read
+};
+
 }  // namespace dhit
 
 struct dhit_box {
@@ -66,6 +76,7 @@ struct dhit_box {
   void *scratch = nullptr;     // DUGKS two-pass transform field
   dhit::StepParams sp{};
   dhit::SpectrumWork *spec = nullptr;
+  dhit::KernelTimer *timer = nullptr;
 };
 
 namespace dhit {
@@ -77,12 +88,22 @@ void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drh
 void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
 void launch_pack(dhit_box &b, const void *f, double *d_out);     // state -> [19][ncell] double
 void launch_unpack(dhit_box &b, const double *d_in, void *f);    // [19][ncell] double -> state
-void launch_finalize_sums(hipStream_t s, const double *partials, int nblocks, double *out);
+void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out);
+void timer_free(dhit_box &b);
 void launch_velocity(dhit_box &b, const void *f, double *d_u);   // u = j / rho0, [3][ncell]
 
 // Spectrum (spectrum.hip)
 void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);
 void spectrum_free(dhit_box &b);
+
+// Event bracket around one kernel launch when timing is enabled:
+//   TimedLaunch t(b, DHIT_K_LBE); hipLaunchKernelGGL(...); t.done();
+struct TimedLaunch {
+  dhit_box &b;
+  int slot = -1;
+  TimedLaunch(dhit_box &box, int kind);
+  void done();
+};
 
 // Number of blocks of a one-cell-per-thread launch over the box.
 inline int cell_blocks(int64_t ncell) { return (int)((ncell + 255) / 256); }

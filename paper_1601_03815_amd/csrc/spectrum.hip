@@ -163,7 +163,7 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
     const int rb = (int)std::min<int64_t>((b.ncell + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(power_sums_kernel, dim3(rb), dim3(kBlock), 0, b.stream, w.u, b.ncell, inv_n3, w.partials);
     DHIT_HIP(hipGetLastError());
-    launch_finalize_sums(b.stream, w.partials, rb, w.dstats + 5 * a);
+    launch_finalize_sums(b, w.partials, rb, w.dstats + 5 * a);
   }
   std::vector<double> sh(2 * w.nshell);
   double ds[15];
