@@ -44,7 +44,7 @@ def kernel_source_hash(kernel):
     files = {"lbe": ["lbe.hip", "collision.hpp", "device_common.hpp", "lattice.hpp"],
              "dugks_face": ["dugks.hip", "device_common.hpp", "lattice.hpp"],
              "dugks_transform": ["dugks.hip", "device_common.hpp", "lattice.hpp"],
-             "dugks_fused": ["dugks_fused.hip", "device_common.hpp", "lattice.hpp"]}.get(kernel, [])
+             "dugks_fused": ["dugks_fused.hip", "collision.hpp", "device_common.hpp", "lattice.hpp"]}.get(kernel, [])
     h = hashlib.sha256()
     for f in files:
         p = os.path.join(csrc, f)

@@ -107,9 +107,20 @@ void derive_step_params(dhit_box &b) {
   s.beta = s.h / (2.0 * s.tau + s.h);
 }
 
+// DUGKS transform field, needed by the two-pass variant only.
 int64_t scratch_bytes_of(const dhit_params &p, int64_t pop_bytes) {
-  (void)p;
-  return pop_bytes;  // DUGKS transform field (allocated for every DUGKS box)
+  return (p.method == DHIT_DUGKS && p.variant == DHIT_VARIANT_TWO_PASS) ? pop_bytes : 0;
+}
+
+// Blocks (and so partial-sum slots) of the largest per-step launch.
+int64_t reduction_blocks(const dhit_params &p) {
+  const int64_t ncell = (int64_t)p.n * p.n * p.n;
+  int64_t blocks = (ncell + 255) / 256;
+  if (p.method == DHIT_DUGKS) {
+    const int64_t f = dhit::fused_dugks_blocks(p.n, nullptr, nullptr, nullptr);
+    if (f > blocks) blocks = f;
+  }
+  return blocks;
 }
 
 void check_finite(const double *s, int count) {
@@ -168,11 +179,7 @@ int64_t population_buffer_bytes(const dhit_params *p) {
 int64_t box_bytes(const dhit_params *p) {
   int64_t pop = population_buffer_bytes(p);
   if (pop < 0) return pop;
-  const int64_t ncell = (int64_t)p->n * p->n * p->n;
-  const int64_t blocks = (ncell + 255) / 256;
-  int64_t total = 2 * pop + blocks * 5 * 8 + dhit::kHistoryCap * 5 * 8;
-  if (p->method == DHIT_DUGKS) total += scratch_bytes_of(*p, pop);
-  return total;
+  return 2 * pop + reduction_blocks(*p) * 5 * 8 + dhit::kHistoryCap * 5 * 8 + scratch_bytes_of(*p, pop);
 }
 
 int32_t create_box(const dhit_params *pp, dhit_box **out) {
@@ -203,11 +210,11 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
         if (hipMalloc(&b->f[0], pop) != hipSuccess || hipMalloc(&b->f[1], pop) != hipSuccess)
           fail(DHIT_ENOMEM, "cannot allocate population buffers");
       }
-      b->max_blocks = dhit::cell_blocks(b->ncell);
+      b->max_blocks = (int)reduction_blocks(*pp);
       if (hipMalloc(&b->partials, (size_t)b->max_blocks * 5 * sizeof(double)) != hipSuccess ||
           hipMalloc(&b->hist, (size_t)dhit::kHistoryCap * 5 * sizeof(double)) != hipSuccess)
         fail(DHIT_ENOMEM, "cannot allocate reduction buffers");
-      if (pp->method == DHIT_DUGKS) {
+      if (scratch_bytes_of(*pp, pop) > 0) {
         if (hipMalloc(&b->scratch, scratch_bytes_of(*pp, pop)) != hipSuccess)
           fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
       }

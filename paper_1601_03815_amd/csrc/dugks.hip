@@ -10,9 +10,11 @@
 //   alpha = 2tau/(2tau+h), beta = h/(2tau+h).
 // Update: f~(t+dt) = f~+ - dt sum_d xi_d (f_face(+d) - f_face(-d))   (dx = 1).
 //
-// This file holds the two-pass form: a transform kernel writes fbp to a
-// scratch field, then a face kernel evaluates the six faces of each cell
-// from that field (through the caches) and writes the update.
+// This file holds the two-pass form (DHIT_VARIANT_TWO_PASS): a transform
+// kernel writes fbp to a scratch field, then a face kernel evaluates the six
+// faces of each cell from that field (through the caches) and writes the
+// update.  It follows the face-by-face description directly and serves as a
+// cross-check of the fused kernel (dugks_fused.hip), which is the default.
 #include "collision.hpp"
 
 namespace dhit {
@@ -151,6 +153,10 @@ static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums
 }
 
 void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  if (b.p.variant == DHIT_VARIANT_DEFAULT) {
+    launch_dugks_fused(b, src, dst, sums_out);
+    return;
+  }
   if (b.p.precision == DHIT_FP64)
     dugks_two_pass<double>(b, src, dst, sums_out);
   else
