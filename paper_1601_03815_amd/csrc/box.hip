@@ -117,7 +117,7 @@ int64_t reduction_blocks(const dhit_params &p) {
   const int64_t ncell = (int64_t)p.n * p.n * p.n;
   int64_t blocks = (ncell + 255) / 256;
   if (p.method == DHIT_DUGKS) {
-    const int64_t f = dhit::fused_dugks_blocks(p.n, nullptr, nullptr, nullptr);
+    const int64_t f = dhit::fused_dugks_blocks(p.n, p.precision, nullptr, nullptr, nullptr);
     if (f > blocks) blocks = f;
   }
   return blocks;

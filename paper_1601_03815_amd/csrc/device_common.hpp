@@ -103,6 +103,28 @@ __device__ __forceinline__ void block_sum5(double (&v)[kNumSums], double (*smem)
   }
 }
 
+// Per-cell contributions to the five global sums, accumulated in FP64 from
+// the stored values (exact for FP32 populations, which double represents).
+template <typename Real>
+__device__ __forceinline__ void sums_of_populations(const Real (&f)[kQ], double inv_rho0, double (&v)[kNumSums]) {
+  double r = 0, ax = 0, ay = 0, az = 0;
+  static_for<kQ>([&](auto q) {
+    const double x = (double)f[q];
+    r += x;
+    if constexpr (kCx[q] == 1) ax += x;
+    if constexpr (kCx[q] == -1) ax -= x;
+    if constexpr (kCy[q] == 1) ay += x;
+    if constexpr (kCy[q] == -1) ay -= x;
+    if constexpr (kCz[q] == 1) az += x;
+    if constexpr (kCz[q] == -1) az -= x;
+  });
+  v[0] += r;
+  v[1] += ax;
+  v[2] += ay;
+  v[3] += az;
+  v[4] += 0.5 * (ax * ax + ay * ay + az * az) * inv_rho0 * inv_rho0;
+}
+
 // Per-cell contributions to the five global sums.
 template <typename Real>
 __device__ __forceinline__ void sums_of_cell(Real drho, Real jx, Real jy, Real jz, double inv_rho0,

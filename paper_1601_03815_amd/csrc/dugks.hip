@@ -122,9 +122,7 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
       o[q] = (Real(4.0 / 3.0) * bp - Real(1.0 / 3.0) * tl) - dt * acc[q];
       out[(int64_t)q * stride + cell] = o[q];
     });
-    Real drho, jx, jy, jz;
-    cell_moments<Real>(o, drho, jx, jy, jz);
-    sums_of_cell<Real>(drho, jx, jy, jz, p.inv_rho0, v);
+    sums_of_populations<Real>(o, p.inv_rho0, v);
   }
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
 }

@@ -39,8 +39,11 @@
 namespace dhit {
 namespace fused {
 
-constexpr int TX = 32, TY = 8, NT = TX * TY;
-constexpr int IX = TX - 2, IY = TY - 2;
+// Column tile of a block: W x 8 columns, the inner (W-2) x 6 updated.
+template <int W>
+struct Tile {
+  static constexpr int TX = W, TY = 8, NT = TX * TY, IX = TX - 2, IY = TY - 2;
+};
 
 // Field ids: 0..18 populations of B; moment fields after them.
 enum : int { kR0 = 19, kJx, kJy, kJz, kPxx, kPxy, kPxz, kPyy, kPyz, kPzz };
@@ -90,8 +93,9 @@ constexpr int pid(int a, int b) {
   return lo == 0 ? (hi == 0 ? kPxx : (hi == 1 ? kPxy : kPxz)) : (lo == 1 ? (hi == 1 ? kPyy : kPyz) : kPzz);
 }
 
-template <typename Real>
+template <typename Real, int W>
 struct Ctx {
+  static constexpr int TX = Tile<W>::TX, NT = Tile<W>::NT;
   const Real *A;  // [3][kNA][NT]
   const Real *B;  // [2][kNB][NT]
   int sa[3];      // A slots of planes centre-1, centre, centre+1
@@ -116,8 +120,8 @@ struct Unit {
 
 // Face moments (drho_b, j_b) of the face between L = centre + (LX, LY, LZ)
 // and R = L + e_D.
-template <int D, int LX, int LY, int LZ, typename Real>
-__device__ __forceinline__ void face_moments(const Ctx<Real> &c, Real h, Real &rho_b, Real (&jb)[3]) {
+template <int D, int LX, int LY, int LZ, typename Real, int W>
+__device__ __forceinline__ void face_moments(const Ctx<Real, W> &c, Real h, Real &rho_b, Real (&jb)[3]) {
   constexpr int RX = LX + Unit<D>::x, RY = LY + Unit<D>::y, RZ = LZ + Unit<D>::z;
   Real tang = Real(0);
   static_for<3>([&](auto t) {
@@ -164,8 +168,8 @@ __device__ __forceinline__ void sub_face_equilibrium(Real rho_b, const Real (&jb
 }
 
 // Linear part L_q of the flux difference (stencil of B_q).
-template <int Q, typename Real>
-__device__ __forceinline__ Real linear_part(const Ctx<Real> &c, Real h) {
+template <int Q, typename Real, int W>
+__device__ __forceinline__ Real linear_part(const Ctx<Real, W> &c, Real h) {
   constexpr int sx = kCx[Q], sy = kCy[Q], sz = kCz[Q];
   constexpr int nz = (sx != 0) + (sy != 0) + (sz != 0);
   const Real b0 = c.template at<Q, 0, 0, 0>();
@@ -206,9 +210,10 @@ __device__ __forceinline__ void load_raw(const Real *__restrict__ ft, int64_t st
 // From the 19 f~ of a cell: moments, B = a f~ + b f^eq, the moment fields of
 // B; writes the fields its neighbours need to the LDS slots (sa, sb) and
 // returns f~+ = 4/3 B - 1/3 f~.
-template <typename Real>
+template <typename Real, int W>
 __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb, Real *A, Real *B, int tid,
                                              const StepParams &p, Real (&ftp)[kQ]) {
+  constexpr int NT = Tile<W>::NT;
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(f, drho, jx, jy, jz);
   equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
@@ -252,10 +257,11 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb
   });
 }
 
-template <typename Real>
-__global__ __launch_bounds__(NT) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
-                                                         StepParams p, int tiles_x, int tiles_y, int nz_chunk,
-                                                         double *__restrict__ partials) {
+template <typename Real, int W>
+__global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
+                                                                  StepParams p, int tiles_x, int tiles_y,
+                                                                  int nz_chunk, double *__restrict__ partials) {
+  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, NT = Tile<W>::NT, IX = Tile<W>::IX, IY = Tile<W>::IY;
   __shared__ Real A[3 * kNA * NT];
   __shared__ Real B[2 * kNB * NT];
   const int n = p.n;
@@ -285,24 +291,24 @@ __global__ __launch_bounds__(NT) void dugks_fused_kernel(const Real *__restrict_
   // prologue: planes z0-1 and z0 published, plane z0+1 in flight, and the
   // z-face between z0-1 and z0
   load_raw<Real>(ft, stride, n, col, z0 - 1, pf);
-  publish_cell<Real>(pf, slot3(z0 - 1), slot2(z0 - 1), A, B, tid, p, acc);
+  publish_cell<Real, W>(pf, slot3(z0 - 1), slot2(z0 - 1), A, B, tid, p, acc);
   load_raw<Real>(ft, stride, n, col, z0, pf);
-  publish_cell<Real>(pf, slot3(z0), slot2(z0), A, B, tid, p, acc);
+  publish_cell<Real, W>(pf, slot3(z0), slot2(z0), A, B, tid, p, acc);
   load_raw<Real>(ft, stride, n, col, z0 + 1, pf);
   __syncthreads();
   {
-    Ctx<Real> c{A, B, {slot3(z0 - 1), slot3(z0), slot3(z0 + 1)}, {slot2(z0 - 1), slot2(z0), slot2(z0 + 1)}, tid};
+    Ctx<Real, W> c{A, B, {slot3(z0 - 1), slot3(z0), slot3(z0 + 1)}, {slot2(z0 - 1), slot2(z0), slot2(z0 + 1)}, tid};
     if (inner && z0 < z1) face_moments<2, 0, 0, -1, Real>(c, h, rho_zm, jzm);
   }
   __syncthreads();
 
   for (int z = z0; z < z1; ++z) {
     // acc holds f~+ of the centre plane z; publish plane z+1, prefetch z+2
-    publish_cell<Real>(pf, slot3(z + 1), slot2(z + 1), A, B, tid, p, ftp_next);
+    publish_cell<Real, W>(pf, slot3(z + 1), slot2(z + 1), A, B, tid, p, ftp_next);
     if (z + 1 < z1) load_raw<Real>(ft, stride, n, col, z + 2, pf);
     __syncthreads();
     if (inner) {
-      Ctx<Real> c{A, B, {slot3(z - 1), slot3(z), slot3(z + 1)}, {slot2(z - 1), slot2(z), slot2(z + 1)}, tid};
+      Ctx<Real, W> c{A, B, {slot3(z - 1), slot3(z), slot3(z + 1)}, {slot2(z - 1), slot2(z), slot2(z + 1)}, tid};
       {
         Real rb, jb[3];
         face_moments<0, 0, 0, 0, Real>(c, h, rb, jb);
@@ -321,10 +327,8 @@ __global__ __launch_bounds__(NT) void dugks_fused_kernel(const Real *__restrict_
         if constexpr (q != 0) acc[q] -= dtal * linear_part<q, Real>(c, h);
       });
       const int cell = z * n * n + col;
-      static_for<kQ>([&](auto q) { out[(int64_t)q * stride + cell] = acc[q]; });
-      Real drho, jx, jy, jz;
-      cell_moments<Real>(acc, drho, jx, jy, jz);
-      sums_of_cell<Real>(drho, jx, jy, jz, p.inv_rho0, v);
+      static_for<kQ>([&](auto q) { __builtin_nontemporal_store(acc[q], &out[(int64_t)q * stride + cell]); });
+      sums_of_populations<Real>(acc, p.inv_rho0, v);
     }
     static_for<kQ>([&](auto q) { acc[q] = ftp_next[q]; });
     __syncthreads();
@@ -334,9 +338,14 @@ __global__ __launch_bounds__(NT) void dugks_fused_kernel(const Real *__restrict_
 
 }  // namespace fused
 
-int fused_dugks_blocks(int n, int *tiles_x, int *tiles_y, int *nz_chunk) {
-  const int tx = (n + fused::IX - 1) / fused::IX;
-  const int ty = (n + fused::IY - 1) / fused::IY;
+// Tile width by precision: FP64 tiles of 16 x 8 columns use 72 KB of LDS,
+// so two blocks share a compute unit; FP32 tiles of 32 x 8 use 72 KB too.
+constexpr int fused_tile_width(int precision) { return precision == DHIT_FP64 ? 16 : 32; }
+
+int fused_dugks_blocks(int n, int precision, int *tiles_x, int *tiles_y, int *nz_chunk) {
+  const int ix = fused_tile_width(precision) - 2, iy = 8 - 2;
+  const int tx = (n + ix - 1) / ix;
+  const int ty = (n + iy - 1) / iy;
   const int cz = n >= 128 ? 32 : (n >= 32 ? 16 : n);
   const int nzc = (n + cz - 1) / cz;
   if (tiles_x) *tiles_x = tx;
@@ -347,11 +356,12 @@ int fused_dugks_blocks(int n, int *tiles_x, int *tiles_y, int *nz_chunk) {
 
 template <typename Real>
 static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  constexpr int W = fused_tile_width(std::is_same<Real, double>::value ? DHIT_FP64 : DHIT_FP32);
   int tx, ty, cz;
-  const int blocks = fused_dugks_blocks(b.n, &tx, &ty, &cz);
+  const int blocks = fused_dugks_blocks(b.n, b.p.precision, &tx, &ty, &cz);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
-    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real>), dim3(blocks), dim3(fused::NT), 0, b.stream,
+    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(blocks), dim3(fused::Tile<W>::NT), 0, b.stream,
                        static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, b.partials);
     DHIT_HIP(hipGetLastError());
     t.done();

@@ -168,11 +168,13 @@ void launch_unpack(dhit_box &b, const double *d_in, void *f) {
   DHIT_HIP(hipGetLastError());
 }
 
-// Plain streaming copy, 16 bytes per thread and iteration.
-__global__ __launch_bounds__(kBlock) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+// Plain streaming copy: 16 bytes per thread, non-temporal loads and stores
+// (the fastest plain copy form measured on MI355X).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                                       int64_t n16) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
-    dst[i] = src[i];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 }  // namespace dhit
@@ -183,9 +185,10 @@ extern "C" int32_t device_copy(void *dst, const void *src, int64_t bytes, void *
     return DHIT_EINVAL;
   const int64_t n16 = bytes / 16;
   if (n16 == 0) return DHIT_OK;
-  const int64_t want = (n16 + dhit::kBlock - 1) / dhit::kBlock;
-  const int blocks = (int)(want < 256 * 64 ? want : 256 * 64);
-  hipLaunchKernelGGL(dhit::copy_kernel, dim3(blocks), dim3(dhit::kBlock), 0, static_cast<hipStream_t>(stream),
-                     static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  const int64_t blocks = (n16 + dhit::kBlock - 1) / dhit::kBlock;
+  if (blocks > 0x7fffffff) return DHIT_EINVAL;
+  hipLaunchKernelGGL(dhit::copy_kernel, dim3((unsigned)blocks), dim3(dhit::kBlock), 0,
+                     static_cast<hipStream_t>(stream), static_cast<const dhit::u32x4 *>(src),
+                     static_cast<dhit::u32x4 *>(dst), n16);
   return hipGetLastError() == hipSuccess ? DHIT_OK : DHIT_EDEVICE;
 }

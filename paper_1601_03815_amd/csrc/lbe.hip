@@ -44,7 +44,8 @@ __global__ __launch_bounds__(kBlock) void lbe_pull_kernel(const Real *__restrict
     cell_moments<Real>(f, drho, jx, jy, jz);
     sums_of_cell<Real>(drho, jx, jy, jz, p.inv_rho0, v);
     collide<C, Real>(f, drho, jx, jy, jz, p);
-    static_for<kQ>([&](auto q) { dst[(int64_t)q * stride + cell] = f[q]; });
+    // the new state is read only by the next step: stream it past the caches
+    static_for<kQ>([&](auto q) { __builtin_nontemporal_store(f[q], &dst[(int64_t)q * stride + cell]); });
   }
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
 }
