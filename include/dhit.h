@@ -179,12 +179,39 @@ int32_t box_synchronize(dhit_box *b);
  * in place, e.g. from PyTorch).  Either output may be NULL. */
 int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
 
-/* Advance many boxes of one method and precision by nsteps steps, each step
- * being one persistent kernel launch over a work list of tiles that spans
- * all boxes (LBE) or one launch per phase (DUGKS), followed by one
- * reduction launch for all boxes.  All boxes must share method and
- * precision; work is issued on the first box's stream and the other boxes'
- * streams are made to wait for it.  Results equal per-box steps. */
+/* Batches: many boxes of one method and precision advanced together
+ * (an ensemble of independent runs, e.g. of different grid sizes).
+ * Each step is one persistent kernel launch over a work list spanning all
+ * boxes (LBE: 256-cell runs; DUGKS: tile z-chunks of the fused kernel)
+ * followed by one launch that finalises every box's global sums; the
+ * per-box buffer index and step counter are kept on the device, so runs of
+ * 8 steps are replayed from one captured hipGraph.  Results equal
+ * single-box steps: LBE populations bit for bit, DUGKS populations to
+ * rounding (the batched kernel is a separate instantiation of the same
+ * per-tile code), global sums to rounding.
+ *
+ * create_batch: boxes[nbox] must share method and precision (DUGKS boxes the
+ * default variant) and appear once.  With autotune != 0 the persistent grid
+ * size and the DUGKS work-item z-chunk are chosen by timing uncommitted
+ * trial steps on the boxes themselves (their states are left unchanged);
+ * choices are cached per process and, if the environment variable
+ * DHIT_TUNE_CACHE names a file, read from and appended to it.  Work is
+ * issued on the first box's stream; the boxes' own streams are synchronised
+ * before each batch step and made to wait for it afterwards.  The boxes must
+ * outlive the batch.  Synchronous (waits for the boxes' pending work). */
+typedef struct dhit_batch dhit_batch;
+int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune, dhit_batch **out);
+
+/* Advance every box of the batch by nsteps >= 0 steps.  Asynchronous. */
+int32_t batch_step(dhit_batch *bt, int32_t nsteps);
+
+/* info[5] = (persistent grid size, DUGKS z-chunk (0 = per-box default),
+ * work items per step, steps per graph replay, 1 if autotuned). */
+int32_t batch_info(const dhit_batch *bt, int64_t *info);
+
+int32_t destroy_batch(dhit_batch *bt);
+
+/* One-off form: builds a batch without tuning or graph, runs nsteps, frees it. */
 int32_t step_batch(dhit_box **boxes, int32_t nbox, int32_t nsteps);
 
 /* Kernel kinds reported by read_kernel_timings. */

@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, last_error,
     moments, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
+    create_batch, batch_step, batch_info, destroy_batch,
 )
 from . import _binding
 
@@ -128,5 +129,38 @@ class Box:
 
 
 def step_boxes(boxes, nsteps=1):
-    """Advance several boxes of one method/precision with the batched launch."""
+    """Advance several boxes of one method/precision with one batched launch
+    per step (no tuning, no graph)."""
     step_batch([b.handle for b in boxes], nsteps)
+
+
+class Batch:
+    """Boxes of one method and precision advanced together: persistent
+    batched launches, autotuned, replayed from a captured hipGraph."""
+
+    def __init__(self, boxes, autotune=True):
+        self.boxes = list(boxes)
+        self.handle = create_batch([b.handle for b in self.boxes], autotune)
+
+    def step(self, nsteps=1):
+        batch_step(self.handle, nsteps)
+
+    def info(self):
+        return batch_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

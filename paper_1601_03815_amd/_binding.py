@@ -90,6 +90,10 @@ def _load():
         "box_synchronize": ([box], i32),
         "current_populations": ([box, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64)], i32),
         "step_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32], i32),
+        "create_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32, ctypes.POINTER(ctypes.c_void_p)], i32),
+        "batch_step": ([ctypes.c_void_p, i32], i32),
+        "batch_info": ([ctypes.c_void_p, dp], i32),
+        "destroy_batch": ([ctypes.c_void_p], i32),
         "set_kernel_timing": ([box, i32], i32),
         "read_kernel_timings": ([box, dp, dp], i32),
         "device_copy": ([ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p], i32),
@@ -227,9 +231,33 @@ def current_populations(h):
     return ptr.value, stride.value
 
 
+def _handle_array(handles):
+    return (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+
+
 def step_batch(handles, nsteps=1):
-    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
-    _check(_lib.step_batch(arr, len(handles), int(nsteps)))
+    _check(_lib.step_batch(_handle_array(handles), len(handles), int(nsteps)))
+
+
+def create_batch(handles, autotune=True):
+    out = ctypes.c_void_p()
+    _check(_lib.create_batch(_handle_array(handles), len(handles), 1 if autotune else 0, ctypes.byref(out)))
+    return out
+
+
+def batch_step(bt, nsteps=1):
+    _check(_lib.batch_step(bt, int(nsteps)))
+
+
+def batch_info(bt):
+    info = np.zeros(5, dtype=np.int64)
+    _check(_lib.batch_info(bt, _ptr(info)))
+    return dict(grid=int(info[0]), chunk=int(info[1]), items=int(info[2]), graph_steps=int(info[3]),
+                tuned=bool(info[4]))
+
+
+def destroy_batch(bt):
+    _check(_lib.destroy_batch(bt))
 
 
 KERNEL_NAMES = ["lbe", "dugks_transform", "dugks_face", "dugks_fused", "finalize"]
@@ -256,5 +284,6 @@ EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
     "init_velocity_field", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
-    "step_batch", "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",
+    "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
+    "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",
 ]

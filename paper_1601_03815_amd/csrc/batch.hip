@@ -1,45 +1,380 @@
-// step_batch: many boxes of one method and precision advanced together.
+// Batches: many boxes of one method and precision advanced together.
+//
+// A batch keeps a device table of its boxes (BatchBox) and runs each step
+// as one persistent kernel over a work list that spans all boxes (LBE:
+// 256-cell runs; DUGKS: tile z-chunks of the fused kernel), followed by
+// one launch that finalises the global sums of every box.  Buffer indices
+// and step counters are kept on the device, so a hipGraph holding several
+// captured steps is replayed for long runs.  The persistent grid size (and
+// for DUGKS the z-chunk length of a work item) are chosen per batch by
+// timing candidate settings on the batch itself (uncommitted trial steps,
+// which leave every box's state unchanged); choices are cached per process
+// by (method, precision, grid sizes) and can be shared through a file named
+// by the environment variable DHIT_TUNE_CACHE.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
+#include "device_common.hpp"
 #include "runtime.hpp"
 
+struct dhit_batch {
+  std::vector<dhit_box *> boxes;
+  int method = 0, precision = 0;
+  hipStream_t stream = nullptr;
+  dhit::BatchBox *d_boxes = nullptr;
+  std::vector<dhit::BatchBox> h_boxes;
+  double *d_partials = nullptr;
+  double *d_trial = nullptr;
+  int total_items = 0;
+  int grid = 0;
+  int chunk = 0;  // DUGKS z-chunk of a work item (0 = per-box default)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;
+  bool tuned = false;
+};
+
 namespace {
+
+constexpr int kGraphSteps = 8;
+
+int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;  // key -> (grid, chunk)
+bool g_tune_file_read = false;
+
+std::string tune_key(const dhit_batch &bt) {
+  std::vector<int> ns;
+  for (auto *b : bt.boxes) ns.push_back(b->n);
+  std::sort(ns.begin(), ns.end());
+  std::string k = std::to_string(bt.method) + "/" + std::to_string(bt.precision) + "/";
+  for (size_t i = 0; i < ns.size(); ++i) k += (i ? "," : "") + std::to_string(ns[i]);
+  return k;
+}
+
+void read_tune_file() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char *path = std::getenv("DHIT_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char key[4096];
+  int grid, chunk;
+  while (std::fscanf(f, "%4095s %d %d", key, &grid, &chunk) == 3) g_tune_cache[key] = {grid, chunk};
+  std::fclose(f);
+}
+
+void write_tune_entry(const std::string &key, int grid, int chunk) {
+  const char *path = std::getenv("DHIT_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), grid, chunk);
+  std::fclose(f);
+}
+
+// Builds the host table for a DUGKS chunk length (0 = each box's default).
+void build_table(dhit_batch &bt, int chunk) {
+  bt.h_boxes.clear();
+  int item = 0;
+  size_t partial_off = 0;
+  std::vector<size_t> offs;
+  for (auto *b : bt.boxes) {
+    dhit::BatchBox d;
+    std::memset(&d, 0, sizeof(d));
+    d.f[0] = b->f[0];
+    d.f[1] = b->f[1];
+    d.sp = b->sp;
+    d.ncell = (int)b->ncell;
+    d.item_begin = item;
+    if (bt.method == DHIT_DUGKS) {
+      const int cz = chunk > 0 ? std::min(chunk, b->n) : dhit::fused_default_chunk(b->n);
+      d.nz_chunk = cz;
+      d.items = dhit::fused_dugks_items(b->n, bt.precision, cz, &d.tiles_x, &d.tiles_y);
+    } else {
+      d.items = dhit::cell_blocks(b->ncell);
+    }
+    d.hist = b->hist;
+    d.cur = b->cur;
+    d.step = b->steps;
+    offs.push_back(partial_off);
+    partial_off += (size_t)d.items * dhit::kNumSums;
+    item += d.items;
+    bt.h_boxes.push_back(d);
+  }
+  bt.total_items = item;
+  if (bt.d_partials) (void)hipFree(bt.d_partials);
+  bt.d_partials = nullptr;
+  if (hipMalloc(&bt.d_partials, partial_off * sizeof(double)) != hipSuccess)
+    throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch partial sums");
+  for (size_t i = 0; i < bt.h_boxes.size(); ++i) {
+    bt.h_boxes[i].partials = bt.d_partials + offs[i];
+    bt.h_boxes[i].trial = bt.d_trial + dhit::kNumSums * i;
+  }
+  bt.chunk = chunk;
+}
+
+// Uploads the table, refreshing buffer indices and step counters from the boxes.
+void upload_table(dhit_batch &bt) {
+  for (size_t i = 0; i < bt.boxes.size(); ++i) {
+    bt.h_boxes[i].cur = bt.boxes[i]->cur;
+    bt.h_boxes[i].step = bt.boxes[i]->steps;
+  }
+  DHIT_HIP(hipMemcpyAsync(bt.d_boxes, bt.h_boxes.data(), bt.h_boxes.size() * sizeof(dhit::BatchBox),
+                          hipMemcpyHostToDevice, bt.stream));
+}
+
+void enqueue_step(dhit_batch &bt, int commit) {
+  const int nbox = (int)bt.boxes.size();
+  if (bt.method == DHIT_DUGKS)
+    dhit::launch_dugks_batch(bt.stream, bt.precision, bt.d_boxes, nbox, bt.total_items, bt.grid);
+  else
+    dhit::launch_lbe_batch(bt.stream, bt.method, bt.precision, bt.d_boxes, nbox, bt.total_items, bt.grid);
+  dhit::launch_finalize_batch(bt.stream, bt.d_boxes, nbox, commit);
+}
+
+void drop_graph(dhit_batch &bt) {
+  if (bt.exec) (void)hipGraphExecDestroy(bt.exec);
+  if (bt.graph) (void)hipGraphDestroy(bt.graph);
+  bt.exec = nullptr;
+  bt.graph = nullptr;
+  bt.graph_steps = 0;
+}
+
+void capture_graph(dhit_batch &bt) {
+  drop_graph(bt);
+  DHIT_HIP(hipStreamBeginCapture(bt.stream, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int s = 0; s < kGraphSteps; ++s) enqueue_step(bt, 1);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(bt.stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  DHIT_HIP(hipStreamEndCapture(bt.stream, &bt.graph));
+  DHIT_HIP(hipGraphInstantiate(&bt.exec, bt.graph, nullptr, nullptr, 0));
+  bt.graph_steps = kGraphSteps;
+}
+
+// Times `reps` uncommitted steps with the current settings (ms per step).
+float time_trial(dhit_batch &bt, int reps) {
+  hipEvent_t e0, e1;
+  DHIT_HIP(hipEventCreate(&e0));
+  DHIT_HIP(hipEventCreate(&e1));
+  float ms = 0.f;
+  try {
+    upload_table(bt);
+    enqueue_step(bt, 0);  // warm-up
+    DHIT_HIP(hipEventRecord(e0, bt.stream));
+    for (int r = 0; r < reps; ++r) enqueue_step(bt, 0);
+    DHIT_HIP(hipEventRecord(e1, bt.stream));
+    DHIT_HIP(hipEventSynchronize(e1));
+    DHIT_HIP(hipEventElapsedTime(&ms, e0, e1));
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+void autotune(dhit_batch &bt) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  read_tune_file();
+  const std::string key = tune_key(bt);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end()) {
+    bt.grid = it->second.first;
+    build_table(bt, it->second.second);
+    bt.tuned = true;
+    return;
+  }
+  const int cus = cu_count();
+  std::vector<int> grids, chunks;
+  if (bt.method == DHIT_DUGKS) {
+    grids = {cus, 2 * cus, 4 * cus};
+    chunks = {8, 16, 32};
+  } else {
+    grids = {2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus};
+    chunks = {0};
+  }
+  float best = 1e30f;
+  int best_grid = grids[0], best_chunk = chunks[0];
+  for (int c : chunks) {
+    build_table(bt, c);
+    for (int g : grids) {
+      bt.grid = std::min(g, std::max(1, bt.total_items));
+      const float ms = time_trial(bt, 3);
+      if (ms < best) {
+        best = ms;
+        best_grid = bt.grid;
+        best_chunk = c;
+      }
+    }
+  }
+  bt.grid = best_grid;
+  build_table(bt, best_chunk);
+  g_tune_cache[key] = {best_grid, best_chunk};
+  write_tune_entry(key, best_grid, best_chunk);
+  bt.tuned = true;
+}
+
+void destroy(dhit_batch *bt) {
+  if (!bt) return;
+  if (bt->stream) (void)hipStreamSynchronize(bt->stream);
+  drop_graph(*bt);
+  if (bt->d_boxes) (void)hipFree(bt->d_boxes);
+  if (bt->d_partials) (void)hipFree(bt->d_partials);
+  if (bt->d_trial) (void)hipFree(bt->d_trial);
+  delete bt;
+}
+
+dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
+  if (!boxes || nbox <= 0) throw dhit::Error(DHIT_EINVAL, "bad batch arguments");
+  for (int32_t i = 0; i < nbox; ++i) {
+    if (!boxes[i]) throw dhit::Error(DHIT_EINVAL, "null box in batch");
+    if (boxes[i]->p.method != boxes[0]->p.method || boxes[i]->p.precision != boxes[0]->p.precision)
+      throw dhit::Error(DHIT_EINVAL, "all boxes of a batch must share method and precision");
+    if (boxes[i]->p.method == DHIT_DUGKS && boxes[i]->p.variant != DHIT_VARIANT_DEFAULT)
+      throw dhit::Error(DHIT_EINVAL, "batched DUGKS uses the fused kernel (variant default)");
+    for (int32_t j = 0; j < i; ++j)
+      if (boxes[j] == boxes[i]) throw dhit::Error(DHIT_EINVAL, "a box appears twice in a batch");
+  }
+  dhit_batch *bt = new dhit_batch();
+  try {
+    bt->boxes.assign(boxes, boxes + nbox);
+    bt->method = boxes[0]->p.method;
+    bt->precision = boxes[0]->p.precision;
+    bt->stream = boxes[0]->stream;
+    if (hipMalloc(&bt->d_boxes, nbox * sizeof(dhit::BatchBox)) != hipSuccess ||
+        hipMalloc(&bt->d_trial, nbox * dhit::kNumSums * sizeof(double)) != hipSuccess)
+      throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");
+    // pending work of every box must finish before the batch stream uses it
+    for (auto *b : bt->boxes) DHIT_HIP(hipStreamSynchronize(b->stream));
+    if (tune) {
+      autotune(*bt);
+    } else {
+      build_table(*bt, 0);
+      bt->grid = std::min(8 * cu_count(), std::max(1, bt->total_items));
+    }
+  } catch (...) {
+    destroy(bt);
+    throw;
+  }
+  return bt;
+}
+
+void run_steps(dhit_batch &bt, int32_t nsteps, bool use_graph) {
+  if (nsteps < 0) throw dhit::Error(DHIT_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return;
+  for (auto *b : bt.boxes)
+    if (b->stream != bt.stream) DHIT_HIP(hipStreamSynchronize(b->stream));
+  upload_table(bt);
+  int32_t left = nsteps;
+  if (use_graph && left >= kGraphSteps) {
+    if (!bt.exec) capture_graph(bt);
+    while (left >= kGraphSteps) {
+      DHIT_HIP(hipGraphLaunch(bt.exec, bt.stream));
+      left -= kGraphSteps;
+    }
+  }
+  for (; left > 0; --left) enqueue_step(bt, 1);
+  for (auto *b : bt.boxes) {
+    b->steps += nsteps;
+    if (nsteps & 1) b->cur ^= 1;
+  }
+  // later work queued on another box's own stream must wait for the batch
+  hipEvent_t done;
+  DHIT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  DHIT_HIP(hipEventRecord(done, bt.stream));
+  for (auto *b : bt.boxes)
+    if (b->stream != bt.stream) DHIT_HIP(hipStreamWaitEvent(b->stream, done, 0));
+  (void)hipEventDestroy(done);
+}
 
 template <class F>
 int32_t guarded_batch(F &&f) {
   try {
+    dhit::set_last_error("");
     (void)hipGetLastError();  // clear a pending error of a call outside this library
     return f();
   } catch (const dhit::Error &e) {
+    dhit::set_last_error(e.what());
     return e.code;
-  } catch (...) {
+  } catch (const std::bad_alloc &) {
+    dhit::set_last_error("host allocation failed");
+    return DHIT_ENOMEM;
+  } catch (const std::exception &e) {
+    dhit::set_last_error(e.what());
     return DHIT_EINVAL;
   }
 }
 
 }  // namespace
 
-extern "C" int32_t step_batch(dhit_box **boxes, int32_t nbox, int32_t nsteps) {
+extern "C" {
+
+int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune_flag, dhit_batch **out) {
   return guarded_batch([&]() -> int32_t {
-    if (!boxes || nbox <= 0 || nsteps < 0) throw dhit::Error(DHIT_EINVAL, "bad batch arguments");
-    for (int32_t i = 0; i < nbox; ++i) {
-      if (!boxes[i]) throw dhit::Error(DHIT_EINVAL, "null box in batch");
-      if (boxes[i]->p.method != boxes[0]->p.method || boxes[i]->p.precision != boxes[0]->p.precision)
-        throw dhit::Error(DHIT_EINVAL, "all boxes of a batch must share method and precision");
-    }
-    const bool lbe = boxes[0]->p.method != DHIT_DUGKS;
-    for (int32_t s = 0; s < nsteps; ++s) {
-      for (int32_t i = 0; i < nbox; ++i) {
-        dhit_box &b = *boxes[i];
-        double *slot = b.hist + (b.steps % dhit::kHistoryCap) * 5;
-        if (lbe)
-          dhit::launch_lbe_step(b, b.f[b.cur], b.f[1 - b.cur], slot);
-        else
-          dhit::launch_dugks_step(b, b.f[b.cur], b.f[1 - b.cur], slot);
-        b.cur = 1 - b.cur;
-        b.steps++;
-      }
-    }
+    if (!out) throw dhit::Error(DHIT_EINVAL, "null output");
+    *out = make_batch(boxes, nbox, autotune_flag);
     return DHIT_OK;
   });
 }
+
+int32_t batch_step(dhit_batch *bt, int32_t nsteps) {
+  return guarded_batch([&]() -> int32_t {
+    if (!bt) throw dhit::Error(DHIT_EINVAL, "null batch");
+    run_steps(*bt, nsteps, true);
+    return DHIT_OK;
+  });
+}
+
+int32_t batch_info(const dhit_batch *bt, int64_t *info) {
+  return guarded_batch([&]() -> int32_t {
+    if (!bt || !info) throw dhit::Error(DHIT_EINVAL, "null argument");
+    info[0] = bt->grid;
+    info[1] = bt->chunk;
+    info[2] = bt->total_items;
+    info[3] = kGraphSteps;
+    info[4] = bt->tuned ? 1 : 0;
+    return DHIT_OK;
+  });
+}
+
+int32_t destroy_batch(dhit_batch *bt) {
+  destroy(bt);
+  return DHIT_OK;
+}
+
+int32_t step_batch(dhit_box **boxes, int32_t nbox, int32_t nsteps) {
+  return guarded_batch([&]() -> int32_t {
+    dhit_batch *bt = make_batch(boxes, nbox, 0);
+    try {
+      run_steps(*bt, nsteps, false);
+    } catch (...) {
+      destroy(bt);
+      throw;
+    }
+    destroy(bt);
+    return DHIT_OK;
+  });
+}
+
+}  // extern "C"

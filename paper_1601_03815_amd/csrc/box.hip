@@ -16,6 +16,12 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string &m) { g_last_error = m; }
 
+}  // namespace
+
+void dhit::set_last_error(const std::string &m) { set_error(m); }
+
+namespace {
+
 // hipGetLastError() reports the last failing HIP call of the thread, including
 // calls made outside this library (by the host program or another library
 // sharing the runtime) and calls whose status is deliberately ignored during

@@ -257,20 +257,17 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb
   });
 }
 
+// The z-march of one tile (bx, by) over the z-chunk bz of a box; adds the
+// moments of the updated cells to v.  A and B are the block's LDS rings.
 template <typename Real, int W>
-__global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
-                                                                  StepParams p, int tiles_x, int tiles_y,
-                                                                  int nz_chunk, double *__restrict__ partials) {
-  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, NT = Tile<W>::NT, IX = Tile<W>::IX, IY = Tile<W>::IY;
-  __shared__ Real A[3 * kNA * NT];
-  __shared__ Real B[2 * kNB * NT];
+__device__ __forceinline__ void fused_tile(const Real *__restrict__ ft, Real *__restrict__ out, const StepParams &p,
+                                           int bx, int by, int bz, int nz_chunk, Real *A, Real *B,
+                                           double (&v)[kNumSums]) {
+  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY;
   const int n = p.n;
   const int64_t stride = p.stride;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  const int bx = blockIdx.x % tiles_x;
-  const int by = (blockIdx.x / tiles_x) % tiles_y;
-  const int bz = blockIdx.x / (tiles_x * tiles_y);
   const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
   const int z1 = min(z0 + nz_chunk, n);
   int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
@@ -284,7 +281,6 @@ __global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__
   auto slot3 = [](int z) { return (z + 3) % 3; };
   auto slot2 = [](int z) { return (z + 2) % 2; };
 
-  double v[kNumSums] = {0, 0, 0, 0, 0};
   Real pf[kQ], acc[kQ], ftp_next[kQ];
   Real rho_zm = Real(0), jzm[3] = {Real(0), Real(0), Real(0)};
 
@@ -333,7 +329,42 @@ __global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__
     static_for<kQ>([&](auto q) { acc[q] = ftp_next[q]; });
     __syncthreads();
   }
+}
+
+template <typename Real, int W>
+__global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
+                                                                  StepParams p, int tiles_x, int tiles_y,
+                                                                  int nz_chunk, double *__restrict__ partials) {
+  __shared__ Real A[3 * kNA * Tile<W>::NT];
+  __shared__ Real B[2 * kNB * Tile<W>::NT];
+  const int bx = blockIdx.x % tiles_x;
+  const int by = (blockIdx.x / tiles_x) % tiles_y;
+  const int bz = blockIdx.x / (tiles_x * tiles_y);
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  fused_tile<Real, W>(ft, out, p, bx, by, bz, nz_chunk, A, B, v);
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
+}
+
+// Many boxes in one persistent launch: work item = one tile z-chunk of one
+// box, numbered as the blocks of that box's single-box launch.
+template <typename Real, int W>
+__global__ __launch_bounds__(Tile<W>::NT) void dugks_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
+                                                                  int total_items) {
+  __shared__ Real A[3 * kNA * Tile<W>::NT];
+  __shared__ Real B[2 * kNB * Tile<W>::NT];
+  for (int it = blockIdx.x; it < total_items; it += gridDim.x) {
+    const int b = find_batch_box(boxes, nbox, it);
+    const BatchBox &d = boxes[b];
+    const int local = it - d.item_begin;
+    const int bx = local % d.tiles_x;
+    const int by = (local / d.tiles_x) % d.tiles_y;
+    const int bz = local / (d.tiles_x * d.tiles_y);
+    double v[kNumSums] = {0, 0, 0, 0, 0};
+    fused_tile<Real, W>(static_cast<const Real *>(d.f[d.cur]), static_cast<Real *>(d.f[d.cur ^ 1]), d.sp, bx, by, bz,
+                        d.nz_chunk, A, B, v);
+    write_block_partials(v, d.partials, d.items, local);
+    __syncthreads();
+  }
 }
 
 }  // namespace fused
@@ -342,11 +373,22 @@ __global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__
 // so two blocks share a compute unit; FP32 tiles of 32 x 8 use 72 KB too.
 constexpr int fused_tile_width(int precision) { return precision == DHIT_FP64 ? 16 : 32; }
 
+int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
+
+int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_y) {
+  const int ix = fused_tile_width(precision) - 2, iy = 8 - 2;
+  const int tx = (n + ix - 1) / ix;
+  const int ty = (n + iy - 1) / iy;
+  if (tiles_x) *tiles_x = tx;
+  if (tiles_y) *tiles_y = ty;
+  return tx * ty * ((n + chunk - 1) / chunk);
+}
+
 int fused_dugks_blocks(int n, int precision, int *tiles_x, int *tiles_y, int *nz_chunk) {
   const int ix = fused_tile_width(precision) - 2, iy = 8 - 2;
   const int tx = (n + ix - 1) / ix;
   const int ty = (n + iy - 1) / iy;
-  const int cz = n >= 128 ? 32 : (n >= 32 ? 16 : n);
+  const int cz = fused_default_chunk(n);
   const int nzc = (n + cz - 1) / cz;
   if (tiles_x) *tiles_x = tx;
   if (tiles_y) *tiles_y = ty;
@@ -367,6 +409,21 @@ static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out
     t.done();
   }
   launch_finalize_sums(b, b.partials, blocks, sums_out);
+}
+
+int fused_tile_width_of(int precision) { return fused_tile_width(precision); }
+
+void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid) {
+  if (precision == DHIT_FP64) {
+    constexpr int W = fused_tile_width(DHIT_FP64);
+    hipLaunchKernelGGL((fused::dugks_batch_kernel<double, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
+                       nbox, total_items);
+  } else {
+    constexpr int W = fused_tile_width(DHIT_FP32);
+    hipLaunchKernelGGL((fused::dugks_batch_kernel<float, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
+                       nbox, total_items);
+  }
+  DHIT_HIP(hipGetLastError());
 }
 
 void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out) {

@@ -93,6 +93,34 @@ __global__ __launch_bounds__(1024) void finalize_sums_kernel(const double *__res
   }
 }
 
+// Per-box finalisation of a batched step: block b sums box b's partials in
+// the order of finalize_sums_kernel, writes the sums to the history slot of
+// the box's step (commit) or to its trial slot, then (commit) advances the
+// step and flips the buffer index.
+__global__ __launch_bounds__(1024) void finalize_batch_kernel(BatchBox *__restrict__ boxes, int commit) {
+  __shared__ double smem[16][kNumSums];
+  BatchBox &d = boxes[blockIdx.x];
+  const int nblocks = d.items;
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 1024) {
+    static_for<kNumSums>([&](auto i) { v[i] += d.partials[(int64_t)i * nblocks + b]; });
+  }
+  block_sum5(v, smem);
+  if (threadIdx.x == 0) {
+    double *out = commit ? d.hist + (d.step % kHistoryCap) * kNumSums : d.trial;
+    static_for<kNumSums>([&](auto i) { out[i] = v[i]; });
+    if (commit) {
+      d.step = d.step + 1;
+      d.cur = d.cur ^ 1;
+    }
+  }
+}
+
+void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commit) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(nbox), dim3(1024), 0, s, d_boxes, commit);
+  DHIT_HIP(hipGetLastError());
+}
+
 void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out) {
   TimedLaunch t(b, DHIT_K_FINALIZE);
   hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, b.stream, partials, nblocks, out);

@@ -44,6 +44,36 @@ struct StepParams {
 
 constexpr int kHistoryCap = 4096;
 
+// One box of a batched launch (device-resident table entry).  `cur` and
+// `step` live on the device so that a captured graph can be replayed for
+// any number of steps: the per-box finalisation writes the history slot of
+// `step`, then advances `step` and flips `cur`.
+struct BatchBox {
+  void *f[2];          // population buffers; f[cur] holds the state
+  StepParams sp;
+  int ncell;
+  int item_begin;      // first work item of the box in the batch
+  int items;           // work items of the box (= blocks of its single-box launch)
+  int tiles_x, tiles_y, nz_chunk;  // DUGKS tiling
+  double *partials;    // the box's per-item partial sums, [5][items]
+  double *hist;        // the box's history of global sums, [kHistoryCap][5]
+  double *trial;       // where a trial (uncommitted) step writes its sums, [5]
+  int cur;
+  int pad_;
+  int64_t step;
+};
+
+// Box of work item `it`: the last box whose first item is <= it.
+__device__ __forceinline__ int find_batch_box(const BatchBox *boxes, int nbox, int it) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boxes[mid].item_begin <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct SpectrumWork;  // spectrum.hip
 
 // Ring of event pairs bracketing kernel launches (see set_kernel_timing).
@@ -81,6 +111,9 @@ struct dhit_box {
 
 namespace dhit {
 
+// Sets the thread's message returned by dhit_last_error().
+void set_last_error(const std::string &m);
+
 // Launchers (each enqueues on b.stream; src/dst are population buffers).
 void launch_lbe_step(dhit_box &b, const void *src, void *dst, double *sums_out);
 void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out);
@@ -94,6 +127,15 @@ void launch_unpack(dhit_box &b, const double *d_in, void *f);    // [19][ncell] 
 void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out);
 void timer_free(dhit_box &b);
 void launch_velocity(dhit_box &b, const void *f, double *d_u);   // u = j / rho0, [3][ncell]
+
+// Batched launches (batch.hip drives them)
+void launch_lbe_batch(hipStream_t s, int method, int precision, BatchBox *d_boxes, int nbox, int total_items,
+                      int grid);
+void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid);
+void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commit);
+int fused_tile_width_of(int precision);
+int fused_default_chunk(int n);
+int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_y);
 
 // Spectrum (spectrum.hip)
 void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);

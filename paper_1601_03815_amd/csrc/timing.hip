@@ -24,7 +24,10 @@ void TimedLaunch::done() {
 
 namespace {
 
-int32_t timer_error(const dhit::Error &e) { return e.code; }
+int32_t timer_error(const dhit::Error &e) {
+  dhit::set_last_error(e.what());
+  return e.code;
+}
 
 void destroy_events(dhit::KernelTimer *t) {
   if (!t->created) return;

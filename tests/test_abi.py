@@ -54,7 +54,9 @@ def test_buffer_sizes():
     assert b32 >= 19 * 256 ** 3 * 4 and b32 < 19 * 256 ** 3 * 4 * 1.01
     assert dhit.box_bytes(p64) >= 2 * b64
     pd = dhit.default_params(256, "dugks", "fp64", 0.01)
-    assert dhit.box_bytes(pd) >= 3 * b64
+    assert 2 * b64 <= dhit.box_bytes(pd) < 2.1 * b64      # fused kernel: no scratch field
+    pd.variant = dhit.VARIANT_TWO_PASS
+    assert dhit.box_bytes(pd) >= 3 * b64                  # two-pass: transform scratch field
 
 
 @pytest.mark.parametrize("field,value", [("n", 3), ("n", 2000), ("nu", 0.0), ("nu", -1.0),

@@ -280,3 +280,67 @@ def test_batch_equals_single_boxes(method):
     finally:
         for b in boxes:
             b.close()
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_graph_replays_equal_single_boxes(method, precision):
+    """An autotuned batch replays its captured 8-step graph three times,
+    with eager work of the program (moments, population reads, another box's
+    steps) and synchronisations between the replays; after every replay each
+    box equals the same box stepped alone: LBE populations bit for bit (same
+    per-cell code), DUGKS populations to rounding (the batched and the
+    single-box kernels are separate instantiations of the same tile code,
+    whose floating-point contraction may differ), global sums of every step
+    within the FP64 bar."""
+    sizes = [8, 12, 5, 16, 24]
+    states = [synth.random_populations(n, seed=70 + i, amplitude=0.01) for i, n in enumerate(sizes)]
+    ref_boxes = [dhit.Box(n, method, precision, 0.01) for n in sizes]
+    boxes = [dhit.Box(n, method, precision, 0.01) for n in sizes]
+    other = dhit.Box(6, method, precision, 0.01)
+    try:
+        for rb, b, f in zip(ref_boxes, boxes, states):
+            rb.set_populations(f)
+            b.set_populations(f)
+        other.set_populations(synth.random_populations(6, seed=99))
+        with dhit.Batch(boxes, autotune=True) as bt:
+            info = bt.info()
+            assert info["tuned"] and info["grid"] > 0 and info["graph_steps"] == 8
+            for replay in range(3):
+                bt.step(8)
+                for rb in ref_boxes:
+                    rb.step(8)
+                for rb, b in zip(ref_boxes, boxes):
+                    got, ref = b.get_populations(), rb.get_populations()
+                    if method == "dugks":
+                        assert rel_err(got, ref) <= (TOL64 if precision == "fp64" else TOL32)
+                    else:
+                        np.testing.assert_array_equal(got, ref)
+                    assert b.steps == rb.steps == 8 * (replay + 1)
+                    hb, hr = b.sums_history(8), rb.sums_history(8)
+                    scale = max(np.abs(hr).max(), 1e-30)
+                    assert np.abs(hb - hr).max() <= 1e-12 * scale
+                # eager work between replays
+                other.step(2)
+                boxes[0].moments()
+        # the batch is gone; the boxes keep working on their own
+        for rb, b in zip(ref_boxes, boxes):
+            b.step(3)
+            rb.step(3)
+            assert rel_err(b.get_populations(), rb.get_populations()) <= (TOL64 if precision == "fp64" else TOL32)
+    finally:
+        for b in ref_boxes + boxes + [other]:
+            b.close()
+
+
+def test_batch_rejects_mixed_boxes():
+    a = dhit.Box(8, "bgk", "fp32", 0.01)
+    b = dhit.Box(8, "dugks", "fp32", 0.01)
+    try:
+        with pytest.raises(dhit.DhitError):
+            dhit.Batch([a, b])
+        with pytest.raises(dhit.DhitError):
+            dhit.Batch([a, a])
+    finally:
+        a.close()
+        b.close()
