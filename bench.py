@@ -116,6 +116,63 @@ def cpu_baseline(n, nu, u256):
             "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4)}
 
 
+def extras(torch, dhit):
+    """Ensemble (64 FP32 boxes), serving (bounded Poisson trace) and FP32-vs-FP64
+    precision reports."""
+    import synth
+    from paper_1601_03815_amd import ensemble, precision, serve
+    out = {}
+    # batched ensemble: 64 realisations, grids from {32, 48, 64, 96}, FP32, nu = 0.01
+    sizes = synth.ensemble_grids(64, (32, 48, 64, 96), seed=0)
+    cells = sum(n ** 3 for n in sizes)
+    ens = {"boxes": 64, "cells": cells, "grid_counts": {str(n): sizes.count(n) for n in sorted(set(sizes))}}
+    for method in ("mrt", "dugks"):
+        print("bench: ensemble %s" % method, file=sys.stderr, flush=True)
+        stream = torch.cuda.Stream()
+        boxes = ensemble.make_ensemble(sizes, method, "fp32", 0.01, stream=stream,
+                                       fields=lambda i, n: synth.dhit_field(n, seed=i + 1, k0=4, u_rms=0.05))
+        steps = 100
+        ms_b, info = ensemble.run_batched(boxes, steps, autotune=True)
+        ms_u = ensemble.run_unbatched(boxes, steps)
+        spec = ensemble.ensemble_spectra(boxes)
+        ens[method] = {"steps": steps, "batched_ms_per_step": round(ms_b / steps, 4),
+                       "batched_mlups": round(cells * steps / (ms_b * 1e-3) / 1e6, 1),
+                       "unbatched_mlups": round(cells * steps / (ms_u * 1e-3) / 1e6, 1),
+                       "batched_eff_GBs": round(cells * 152 * steps / (ms_b * 1e-3) / 1e9, 1),
+                       "tuning": info,
+                       "mean_K_by_grid": {str(n): v[2] for n, v in spec.items()},
+                       "mean_E_k1_k4_by_grid": {str(n): [float(x) for x in v[0][1:5]] for n, v in spec.items()}}
+        for b in boxes:
+            b.close()
+        torch.cuda.empty_cache()
+    out["ensemble"] = ens
+    # serving: bounded trace, FP32, two HBM budgets
+    srv = {}
+    for label, budget, count in (("full_hbm", 250e9, 40), ("budget_16GB", 16e9, 40)):
+        print("bench: serving %s" % label, file=sys.stderr, flush=True)
+        trace = serve.poisson_trace(count, 20.0, seed=7)
+        be = serve.GpuBackend(precision="fp32", nu=0.01)
+        st = serve.Scheduler(be, budget, max_active=64, chunk=64).run(trace)
+        st["offered_rate_per_s"] = 20.0
+        srv[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        torch.cuda.empty_cache()
+    out["serving"] = srv
+    # precision: FP32 vs FP64 spectra at 256^3, nu = 0.0025 and at 64^3 nu = 0.01
+    prec = {}
+    for n, nu, steps, every in ((256, 0.0025, 400, 100), (64, 0.01, 800, 100)):
+        for method in ("mrt", "dugks"):
+            print("bench: precision %s %d" % (method, n), file=sys.stderr, flush=True)
+            u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
+            k = steps if method == "mrt" else 2 * steps
+            rep, hz = precision.compare_fp32_fp64(u, method, nu, k, every if method == "mrt" else 2 * every)
+            prec["%s_%d" % (method, n)] = {"steps": k, "horizon_1e-4": hz,
+                                             "outputs": [{kk: (round(vv, 8) if isinstance(vv, float) else vv)
+                                                          for kk, vv in r.items()} for r in rep]}
+            torch.cuda.empty_cache()
+    out["precision"] = prec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +182,8 @@ def main():
     ap.add_argument("--nu", type=float, default=0.0025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the ensemble, serving and precision configurations (minutes)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -249,6 +308,8 @@ def main():
         line["mlups_fp32"] = {"combined": round(r["mlups"], 1), "lbe_mrt": round(r["mlups_lbe_mrt"], 1),
                               "dugks": round(r["mlups_dugks"], 1),
                               "speedup_vs_fp64": round(r["mlups"] / fp64["mlups"], 3)}
+    if args.extras:
+        line["extras"] = extras(torch, dhit)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, nu, u)

@@ -16,6 +16,10 @@ from ._binding import (  # noqa: F401
 )
 from . import _binding
 
+import itertools as _itertools
+
+_uids = _itertools.count()
+
 
 class Box:
     """One periodic n^3 box of one method and precision.
@@ -32,6 +36,7 @@ class Box:
     """
 
     def __init__(self, n, method, precision="fp64", nu=0.01, torch_memory=True, stream=None, **overrides):
+        self.uid = next(_uids)   # unique for the process (never reused, unlike id())
         self.n = int(n)
         self.method = method
         self.params = default_params(n, method, precision, nu)

@@ -30,8 +30,10 @@ __global__ __launch_bounds__(kBlock) void dugks_transform_kernel(const Real *__r
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(f, drho, jx, jy, jz);
   equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
-  const Real a = Real(p.a_bp), b = Real(p.b_bp);
-  static_for<kQ>([&](auto q) { fbp[(int64_t)q * stride + cell] = a * f[q] + b * feq[q]; });
+  // fbp = a f~ + b f^eq with a + b = 1, written as f^eq + a (f~ - f^eq) so
+  // that an equilibrium cell maps to itself exactly in any precision
+  const Real a = Real(p.a_bp);
+  static_for<kQ>([&](auto q) { fbp[(int64_t)q * stride + cell] = feq[q] + a * (f[q] - feq[q]); });
 }
 
 // Offsets of the 3x3x3 neighbourhood of a cell: off(dx,dy,dz) = X[dx] + Y[dy] + Z[dz].
@@ -119,7 +121,8 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
     static_for<kQ>([&](auto q) {
       const Real bp = fbp[(int64_t)q * stride + cell];
       const Real tl = ft[(int64_t)q * stride + cell];
-      o[q] = (Real(4.0 / 3.0) * bp - Real(1.0 / 3.0) * tl) - dt * acc[q];
+      // f~+ = 4/3 fbp - 1/3 f~ = fbp + (fbp - f~)/3 (exact when fbp = f~)
+      o[q] = (bp + (bp - tl) * Real(1.0 / 3.0)) - dt * acc[q];
       out[(int64_t)q * stride + cell] = o[q];
     });
     sums_of_populations<Real>(o, p.inv_rho0, v);

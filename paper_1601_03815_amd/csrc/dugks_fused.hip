@@ -231,25 +231,32 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb
     if constexpr (y * z == 1) pyz += f[q];
     if constexpr (y * z == -1) pyz -= f[q];
   });
-  const Real a = Real(p.a_bp), b = Real(p.b_bp);
+  // B = a f~ + b f^eq with a + b = 1 is formed as f^eq + a (f~ - f^eq) and
+  // f~+ = 4/3 B - 1/3 f~ as B + (B - f~)/3, so that an equilibrium cell maps
+  // to itself exactly in any precision (rounded 4/3 and 1/3, or a and b,
+  // would otherwise scale the state by 1 + O(ulp) every step)
+  const Real a = Real(p.a_bp);
   const Real ir = Real(p.inv_rho0);
   const Real d3 = drho * Real(1.0 / 3.0);
   Real fld[29];
   static_for<kQ>([&](auto q) {
-    const Real bp = a * f[q] + b * feq[q];
+    const Real bp = feq[q] + a * (f[q] - feq[q]);
     fld[q] = bp;
-    ftp[q] = Real(4.0 / 3.0) * bp - Real(1.0 / 3.0) * f[q];
+    ftp[q] = bp + (bp - f[q]) * Real(1.0 / 3.0);
   });
   fld[kR0] = drho;
   fld[kJx] = jx;
   fld[kJy] = jy;
   fld[kJz] = jz;
-  fld[kPxx] = a * pxx + b * (d3 + jx * jx * ir);
-  fld[kPyy] = a * pyy + b * (d3 + jy * jy * ir);
-  fld[kPzz] = a * pzz + b * (d3 + jz * jz * ir);
-  fld[kPxy] = a * pxy + b * (jx * jy * ir);
-  fld[kPxz] = a * pxz + b * (jx * jz * ir);
-  fld[kPyz] = a * pyz + b * (jy * jz * ir);
+  // P = a Pi(f~) + b Pi(f^eq), Pi(f^eq) = drho/3 I + j j / rho0, in the same form
+  const Real exx = d3 + jx * jx * ir, eyy = d3 + jy * jy * ir, ezz = d3 + jz * jz * ir;
+  const Real exy = jx * jy * ir, exz = jx * jz * ir, eyz = jy * jz * ir;
+  fld[kPxx] = exx + a * (pxx - exx);
+  fld[kPyy] = eyy + a * (pyy - eyy);
+  fld[kPzz] = ezz + a * (pzz - ezz);
+  fld[kPxy] = exy + a * (pxy - exy);
+  fld[kPxz] = exz + a * (pxz - exz);
+  fld[kPyz] = eyz + a * (pyz - eyz);
   static_for<29>([&](auto id) {
     constexpr int ia = a_index(id), ib = b_index(id);
     if constexpr (ia >= 0) A[(sa * kNA + ia) * NT + tid] = fld[id];

@@ -1,0 +1,209 @@
+"""Continuous-batching serving loop for decaying-turbulence runs.
+
+Requests (grid size, method, number of steps, seed) arrive over time.  The
+scheduler admits a waiting request when its device memory fits the HBM
+budget and a slot is free, keeps every admitted run's populations resident
+on the device, and advances all active runs together: the runs of each
+method form one batch (one persistent launch per step for all of them, on
+that method's stream, so the two methods' work overlaps on the device).
+The active set is re-formed whenever a run finishes or is admitted, between
+chunks of steps, so requests that arrive while others are running join
+without waiting for them to finish.  A finished run's energy spectrum and
+statistics are computed on the device, its memory is released, and the
+latency from arrival to result is recorded.
+
+The scheduler talks to a backend object (GPU: `GpuBackend`; tests use a fake
+one) with these methods:
+    bytes_of(req) -> int       device bytes the run needs while active
+    start(req) -> handle       allocate and initialise the run
+    advance(handles, nsteps)   advance active runs (all of one method) by nsteps
+    finish(handle) -> result   final diagnostics of a finished run
+    release(handle)            free the run's device memory
+    sync()                     wait for all queued work
+"""
+import heapq
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(order=True)
+class Request:
+    arrival: float
+    rid: int = field(compare=False)
+    n: int = field(compare=False)
+    method: str = field(compare=False)
+    steps: int = field(compare=False)
+    seed: int = field(compare=False)
+
+
+def poisson_trace(count, rate, seed, grids=(32, 64, 128, 256), weights=(0.4, 0.3, 0.2, 0.1),
+                  methods=("mrt", "dugks"), steps=(500, 2000)):
+    """`count` requests with exponential inter-arrival times of mean 1/rate
+    seconds; grid, method and step count drawn independently."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    w = np.asarray(weights, dtype=float)
+    w = w / w.sum()
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.choice(np.asarray(grids), p=w))
+        m = methods[int(rng.integers(len(methods)))]
+        k = int(rng.integers(steps[0], steps[1] + 1))
+        out.append(Request(arrival=t, rid=i, n=n, method=m, steps=k, seed=1000 + i))
+    return out
+
+
+@dataclass
+class Active:
+    req: Request
+    handle: object
+    bytes: int
+    done: int = 0
+    admitted: float = 0.0
+
+
+class Scheduler:
+    """Admits requests by HBM budget and slot count, advances the active
+    runs in chunks of at most `chunk` steps (a chunk never runs a request
+    past its step count), finishes and releases completed runs."""
+
+    def __init__(self, backend, budget_bytes, max_active=64, chunk=64):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.active = []
+        self.results = {}
+
+    def _admit(self, waiting, now):
+        admitted = []
+        while waiting and waiting[0].arrival <= now and len(self.active) < self.max_active:
+            req = waiting[0]
+            need = self.backend.bytes_of(req)
+            if need > self.budget:
+                raise ValueError("request %d needs %d bytes, more than the whole budget" % (req.rid, need))
+            if self.in_use + need > self.budget:
+                break   # first come, first served: later arrivals wait behind it
+            heapq.heappop(waiting)
+            h = self.backend.start(req)
+            self.in_use += need
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            a = Active(req, h, need, 0, now)
+            self.active.append(a)
+            admitted.append(a)
+        return admitted
+
+    def run(self, trace, clock=time.perf_counter, sleep=time.sleep, on_result=None):
+        waiting = list(trace)
+        heapq.heapify(waiting)
+        t0 = clock()
+        cells_steps = 0
+        while waiting or self.active:
+            now = clock() - t0
+            self._admit(waiting, now)
+            if not self.active:
+                if waiting:
+                    sleep(max(0.0, waiting[0].arrival - (clock() - t0)))
+                continue
+            k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
+            groups = {}
+            for a in self.active:
+                groups.setdefault(a.req.method, []).append(a)
+            for method, acts in groups.items():
+                self.backend.advance([a.handle for a in acts], k)
+            for a in self.active:
+                a.done += k
+                cells_steps += a.req.n ** 3 * k
+            finished = [a for a in self.active if a.done >= a.req.steps]
+            for a in finished:
+                res = self.backend.finish(a.handle)
+                t_done = clock() - t0
+                self.results[a.req.rid] = dict(result=res, latency=t_done - a.req.arrival,
+                                               wait=a.admitted - a.req.arrival, n=a.req.n,
+                                               method=a.req.method, steps=a.req.steps)
+                self.backend.release(a.handle)
+                self.in_use -= a.bytes
+                if on_result:
+                    on_result(a.req, self.results[a.req.rid])
+            self.active = [a for a in self.active if a.done < a.req.steps]
+        self.backend.sync()
+        wall = clock() - t0
+        lat = np.array([r["latency"] for r in self.results.values()])
+        return dict(requests=len(self.results), wall_s=wall,
+                    p50_s=float(np.percentile(lat, 50)) if len(lat) else math.nan,
+                    p99_s=float(np.percentile(lat, 99)) if len(lat) else math.nan,
+                    mean_s=float(lat.mean()) if len(lat) else math.nan,
+                    mlups=cells_steps / wall / 1e6 if wall > 0 else math.nan,
+                    peak_bytes=self.peak_in_use)
+
+
+class GpuBackend:
+    """Runs requests as library boxes on the current GPU: FP32 by default,
+    one PyTorch stream per method, one batch per method and chunk."""
+
+    def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None):
+        import torch
+
+        from . import Batch, Box, box_bytes, default_params
+        self._torch = torch
+        self._Box, self._Batch = Box, Batch
+        self._box_bytes, self._default_params = box_bytes, default_params
+        self.precision, self.nu, self.k0, self.u_rms = precision, nu, k0, u_rms
+        self.streams = {}
+        self.batches = {}   # method -> (uids of its boxes, Batch)
+        if fields is None:
+            import synth
+            fields = lambda req: synth.dhit_field(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
+        self.fields = fields
+
+    def _stream(self, method):
+        if method not in self.streams:
+            self.streams[method] = self._torch.cuda.Stream()
+        return self.streams[method]
+
+    def bytes_of(self, req):
+        p = self._default_params(req.n, req.method, self.precision, self.nu)
+        # the spectrum work space (u, u_hat, derivative spectrum: ~64 n^3 bytes) is
+        # allocated when the run finishes; count it while the run is active
+        return self._box_bytes(p) + 64 * req.n ** 3
+
+    def start(self, req):
+        b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._stream(req.method))
+        b.init_velocity_field(self.fields(req))
+        return b
+
+    def advance(self, boxes, nsteps):
+        # a batch lives as long as its set of runs: it is re-formed only when
+        # a run joins or leaves the method's active set
+        key = tuple(b.uid for b in boxes)
+        method = boxes[0].method
+        cur = self.batches.get(method)
+        if cur is None or cur[0] != key:
+            if cur is not None:
+                cur[1].close()
+            self.batches[method] = (key, self._Batch(boxes, autotune=False))
+        self.batches[method][1].step(nsteps)
+
+    def finish(self, box):
+        E, st = box.energy_spectrum(box.n // 2)
+        return dict(E=E, **st)
+
+    def release(self, box):
+        # a batch that holds this run is closed first (it would hold a freed box)
+        for method, (key, bt) in list(self.batches.items()):
+            if box.uid in key:
+                bt.close()
+                del self.batches[method]
+        box.close()
+
+    def sync(self):
+        for _, bt in self.batches.values():
+            bt.close()
+        self.batches = {}
+        self._torch.cuda.synchronize()

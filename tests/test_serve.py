@@ -1,0 +1,130 @@
+"""Serving loop: scheduler logic on the CPU with a fake backend, and on the
+GPU the requirement that each result is the same alone and in the mix."""
+import numpy as np
+import pytest
+
+from paper_1601_03815_amd.serve import Request, Scheduler, poisson_trace
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(0.0, dt)
+
+
+class FakeBackend:
+    """Simulated device: a run of n^3 cells costs n^3 * steps / rate seconds
+    of device time; memory is 2 * 8 * 19 * n^3 bytes."""
+
+    def __init__(self, clock, rate=1e9):
+        self.clock, self.rate = clock, rate
+        self.live = {}
+        self.steps = {}
+        self.order = []
+
+    def bytes_of(self, req):
+        return 2 * 8 * 19 * req.n ** 3
+
+    def start(self, req):
+        self.live[req.rid] = req
+        self.steps[req.rid] = 0
+        self.order.append(req.rid)
+        return req.rid
+
+    def advance(self, handles, nsteps):
+        cost = sum(self.live[h].n ** 3 for h in handles) * nsteps / self.rate
+        self.clock.t += cost
+        for h in handles:
+            self.steps[h] += nsteps
+
+    def finish(self, h):
+        return {"steps": self.steps[h]}
+
+    def release(self, h):
+        del self.live[h]
+
+    def sync(self):
+        pass
+
+
+def test_trace_is_seeded_and_shaped():
+    a = poisson_trace(200, 20.0, seed=3)
+    b = poisson_trace(200, 20.0, seed=3)
+    assert [(r.arrival, r.n, r.method, r.steps) for r in a] == [(r.arrival, r.n, r.method, r.steps) for r in b]
+    assert all(x.arrival < y.arrival for x, y in zip(a, a[1:]))
+    assert {r.n for r in a} <= {32, 64, 128, 256} and {r.method for r in a} == {"mrt", "dugks"}
+    assert all(500 <= r.steps <= 2000 for r in a)
+    gaps = np.diff([0.0] + [r.arrival for r in a])
+    assert 0.03 < gaps.mean() < 0.07            # mean 1/20 s
+
+
+@pytest.mark.parametrize("budget_gb,max_active", [(1000.0, 64), (16.0, 64), (16.0, 3)])
+def test_scheduler_budget_order_and_completion(budget_gb, max_active):
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    trace = poisson_trace(60, 20.0, seed=5)
+    sch = Scheduler(be, budget_gb * 1e9, max_active=max_active, chunk=64)
+    stats = sch.run(trace, clock=clock, sleep=clock.sleep)
+    assert stats["requests"] == 60
+    assert sch.peak_in_use <= budget_gb * 1e9
+    assert not be.live and sch.in_use == 0
+    for r in trace:                              # every run got exactly its steps
+        res = sch.results[r.rid]
+        assert res["result"]["steps"] == r.steps
+        assert res["latency"] >= r.n ** 3 * r.steps / be.rate - 1e-9
+        assert res["wait"] >= 0
+    assert be.order == sorted(be.order)          # admitted first come, first served
+    assert stats["p99_s"] >= stats["p50_s"] > 0
+
+
+def test_scheduler_admits_while_others_run():
+    """A request arriving while a long run is active starts before that run ends."""
+    clock = FakeClock()
+    be = FakeBackend(clock, rate=1e6)
+    trace = [Request(0.0, 0, 64, "mrt", 2000, 1), Request(0.01, 1, 32, "dugks", 100, 2)]
+    sch = Scheduler(be, 1e12, chunk=50)
+    sch.run(trace, clock=clock, sleep=clock.sleep)
+    assert sch.results[1]["latency"] < sch.results[0]["latency"]
+    assert sch.results[1]["wait"] < 64 ** 3 * 2000 / be.rate
+
+
+def test_scheduler_rejects_oversized_request():
+    clock = FakeClock()
+    sch = Scheduler(FakeBackend(clock), 1e6)
+    with pytest.raises(ValueError):
+        sch.run([Request(0.0, 0, 64, "mrt", 10, 1)], clock=clock, sleep=clock.sleep)
+
+
+@pytest.mark.gpu
+def test_result_is_the_same_alone_and_in_the_mix():
+    """Runs served together (continuous batching, both methods overlapping on
+    two streams) give the same spectra as each run alone on its own box.
+    LBE populations are identical bit for bit, so LBE spectra agree to the
+    shell sums' own summation order (atomic adds, ~1e-16); DUGKS spectra
+    agree to FP32 rounding."""
+    import paper_1601_03815_amd as dhit
+    import synth
+    from paper_1601_03815_amd.serve import GpuBackend
+
+    trace = poisson_trace(12, 200.0, seed=11, grids=(8, 12, 16), weights=(1, 1, 1), steps=(20, 60))
+    be = GpuBackend(precision="fp32", nu=0.01)
+    sch = Scheduler(be, 4e9, chunk=16)
+    stats = sch.run(trace)
+    assert stats["requests"] == len(trace)
+    for r in trace:
+        with dhit.Box(r.n, r.method, "fp32", 0.01) as b:
+            b.init_velocity_field(synth.dhit_field(r.n, seed=r.seed, k0=4.0, u_rms=0.05))
+            b.step(r.steps)
+            E, st = b.energy_spectrum(r.n // 2)
+        got = sch.results[r.rid]["result"]
+        if r.method == "dugks":
+            assert np.abs(got["E"] - E).max() <= 1e-6 * E.max()
+            assert abs(got["K"] / st["K"] - 1) <= 1e-6
+        else:
+            assert np.abs(got["E"] - E).max() <= 1e-12 * E.max()
+            assert abs(got["K"] / st["K"] - 1) <= 1e-12
