@@ -151,18 +151,51 @@ __device__ __forceinline__ void face_moments(const Ctx<Real, W> &c, Real h, Real
   });
 }
 
-// acc_q -= dt beta S xi_qD f^eq_q(face) for the populations crossing a
+// Index of the population with velocity (x, y, z).
+constexpr int pop_of(int x, int y, int z) {
+  for (int q = 0; q < kQ; ++q)
+    if (kCx[q] == x && kCy[q] == y && kCz[q] == z) return q;
+  return -1;
+}
+
+// acc_q -= dt beta S xi_qD f^eq_q(face) for the ten populations crossing a
 // D-face (the face-equilibrium part of the flux difference, subtracted from
-// f~+ as each face is evaluated).
+// f~+ as each face is evaluated).  With u = j_b/rho0 and
+// f^eq_q = W_q [rho_b - 3/2 rho0 |u|^2 + 3 rho0 (xi.u) + 9/2 rho0 (xi.u)^2],
+// opposite velocities share the even part and flip the odd part, so each
+// pair is formed from one even and one odd term.
 template <int D, int S, typename Real>
 __device__ __forceinline__ void sub_face_equilibrium(Real rho_b, const Real (&jb)[3], const StepParams &p, Real dtbe,
                                                      Real (&acc)[kQ]) {
-  Real feq[kQ];
-  equilibrium<Real>(rho_b, jb[0], jb[1], jb[2], Real(p.rho0), Real(p.inv_rho0), feq);
-  static_for<kQ>([&](auto q) {
-    if constexpr (cdir(q, D) != 0) {
-      if constexpr (S * cdir(q, D) > 0) acc[q] -= dtbe * feq[q];
-      else acc[q] += dtbe * feq[q];
+  const Real rho0 = Real(p.rho0), ir = Real(p.inv_rho0);
+  const Real u[3] = {jb[0] * ir, jb[1] * ir, jb[2] * ir};
+  const Real base = rho_b - Real(1.5) * rho0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const Real c3 = Real(3) * rho0, c45 = Real(4.5) * rho0;
+  const Real k1 = Real(S) * dtbe * Real(1.0 / 18.0), k2 = Real(S) * dtbe * Real(1.0 / 36.0);
+  const Real ud = u[D];
+  {
+    const Real ev = base + c45 * ud * ud, od = c3 * ud;
+    constexpr int qp = pop_of(Unit<D>::x, Unit<D>::y, Unit<D>::z);
+    constexpr int qm = pop_of(-Unit<D>::x, -Unit<D>::y, -Unit<D>::z);
+    acc[qp] -= k1 * (ev + od);   // xi_D = +1
+    acc[qm] += k1 * (ev - od);   // xi_D = -1
+  }
+  static_for<3>([&](auto t) {
+    if constexpr (t != D) {
+      const Real ut = u[t];
+      const Real up = ud + ut, um = ud - ut;
+      const Real ep = base + c45 * up * up, op = c3 * up;
+      const Real em = base + c45 * um * um, om = c3 * um;
+      constexpr int x = Unit<D>::x, y = Unit<D>::y, z = Unit<D>::z;
+      constexpr int tx = Unit<t>::x, ty = Unit<t>::y, tz = Unit<t>::z;
+      constexpr int q_pp = pop_of(x + tx, y + ty, z + tz);      // xi.u = ud + ut
+      constexpr int q_pm = pop_of(x - tx, y - ty, z - tz);      // xi.u = ud - ut
+      constexpr int q_mp = pop_of(-x + tx, -y + ty, -z + tz);   // xi.u = -(ud - ut)
+      constexpr int q_mm = pop_of(-x - tx, -y - ty, -z - tz);   // xi.u = -(ud + ut)
+      acc[q_pp] -= k2 * (ep + op);
+      acc[q_pm] -= k2 * (em + om);
+      acc[q_mp] += k2 * (em - om);
+      acc[q_mm] += k2 * (ep - op);
     }
   });
 }
