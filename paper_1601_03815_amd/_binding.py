@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
     """Mirror of struct dhit_params."""
     _fields_ = [
         ("n", ctypes.c_int32), ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("variant", ctypes.c_int32),
+        ("variant", ctypes.c_int32), ("tile_width", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
         ("nu", ctypes.c_double), ("rho0", ctypes.c_double), ("dt", ctypes.c_double),
         ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("s4", ctypes.c_double), ("s9", ctypes.c_double),
         ("s10", ctypes.c_double), ("s13", ctypes.c_double), ("s16", ctypes.c_double),

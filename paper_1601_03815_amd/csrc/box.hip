@@ -69,6 +69,8 @@ void validate(const dhit_params &p) {
   if (p.method < DHIT_LBE_BGK || p.method > DHIT_DUGKS) fail(DHIT_EINVAL, "unknown method");
   if (p.precision != DHIT_FP64 && p.precision != DHIT_FP32) fail(DHIT_EINVAL, "unknown precision");
   if (p.variant != DHIT_VARIANT_DEFAULT && p.variant != DHIT_VARIANT_TWO_PASS) fail(DHIT_EINVAL, "unknown variant");
+  if (p.tile_width != 0 && p.tile_width != 16 && p.tile_width != 32) fail(DHIT_EINVAL, "tile_width must be 0, 16 or 32");
+  if (p.z_chunk < 0 || p.z_chunk > p.n) fail(DHIT_EINVAL, "z_chunk must be in [0, n]");
   if (!(p.nu > 0) || !std::isfinite(p.nu)) fail(DHIT_EINVAL, "nu must be positive and finite");
   if (!(p.rho0 > 0) || !std::isfinite(p.rho0)) fail(DHIT_EINVAL, "rho0 must be positive and finite");
   if (p.method == DHIT_DUGKS) {
@@ -123,7 +125,7 @@ int64_t reduction_blocks(const dhit_params &p) {
   const int64_t ncell = (int64_t)p.n * p.n * p.n;
   int64_t blocks = (ncell + 255) / 256;
   if (p.method == DHIT_DUGKS) {
-    const int64_t f = dhit::fused_dugks_blocks(p.n, p.precision, nullptr, nullptr, nullptr);
+    const int64_t f = dhit::fused_dugks_blocks(p, nullptr, nullptr, nullptr, nullptr);
     if (f > blocks) blocks = f;
   }
   return blocks;

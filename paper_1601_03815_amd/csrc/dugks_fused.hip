@@ -409,8 +409,8 @@ __global__ __launch_bounds__(Tile<W>::NT) void dugks_batch_kernel(BatchBox *__re
 
 }  // namespace fused
 
-// Tile width by precision: FP64 tiles of 16 x 8 columns use 72 KB of LDS,
-// so two blocks share a compute unit; FP32 tiles of 32 x 8 use 72 KB too.
+// Default tile width by precision: FP64 tiles of 16 x 8 columns use 72 KB of
+// LDS, so two blocks share a compute unit; FP32 tiles of 32 x 8 use 72 KB too.
 constexpr int fused_tile_width(int precision) { return precision == DHIT_FP64 ? 16 : 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
@@ -424,27 +424,38 @@ int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_
   return tx * ty * ((n + chunk - 1) / chunk);
 }
 
-int fused_dugks_blocks(int n, int precision, int *tiles_x, int *tiles_y, int *nz_chunk) {
-  const int ix = fused_tile_width(precision) - 2, iy = 8 - 2;
+// Blocks of a single-box fused launch with the box's tile width and z-chunk.
+int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
+  const int n = p.n;
+  const int w = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
+  const int ix = w - 2, iy = 8 - 2;
   const int tx = (n + ix - 1) / ix;
   const int ty = (n + iy - 1) / iy;
-  const int cz = fused_default_chunk(n);
+  const int cz = p.z_chunk ? p.z_chunk : fused_default_chunk(n);
   const int nzc = (n + cz - 1) / cz;
+  if (width) *width = w;
   if (tiles_x) *tiles_x = tx;
   if (tiles_y) *tiles_y = ty;
   if (nz_chunk) *nz_chunk = cz;
   return tx * ty * nzc;
 }
 
+template <typename Real, int W>
+static void fused_launch(dhit_box &b, const void *src, void *dst, int blocks, int tx, int ty, int cz) {
+  hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(blocks), dim3(fused::Tile<W>::NT), 0, b.stream,
+                     static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, b.partials);
+}
+
 template <typename Real>
 static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
-  constexpr int W = fused_tile_width(std::is_same<Real, double>::value ? DHIT_FP64 : DHIT_FP32);
-  int tx, ty, cz;
-  const int blocks = fused_dugks_blocks(b.n, b.p.precision, &tx, &ty, &cz);
+  int w, tx, ty, cz;
+  const int blocks = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
-    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(blocks), dim3(fused::Tile<W>::NT), 0, b.stream,
-                       static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, b.partials);
+    if (w == 16)
+      fused_launch<Real, 16>(b, src, dst, blocks, tx, ty, cz);
+    else
+      fused_launch<Real, 32>(b, src, dst, blocks, tx, ty, cz);
     DHIT_HIP(hipGetLastError());
     t.done();
   }

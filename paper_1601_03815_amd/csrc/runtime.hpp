@@ -119,7 +119,7 @@ void launch_lbe_step(dhit_box &b, const void *src, void *dst, double *sums_out);
 void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out);
 void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out);
 // Blocks of the fused DUGKS launch for an n^3 box (and its tiling).
-int fused_dugks_blocks(int n, int precision, int *tiles_x, int *tiles_y, int *nz_chunk);
+int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk);
 void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst);
 void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
 void launch_pack(dhit_box &b, const void *f, double *d_out);     // state -> [19][ncell] double

@@ -344,3 +344,20 @@ def test_batch_rejects_mixed_boxes():
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile,chunk", [(16, 0), (32, 0), (16, 5), (32, 7), (16, 1)])
+def test_dugks_tile_and_chunk_settings(precision, tile, chunk):
+    """Every tile width and z-chunk (including chunks that do not divide n
+    and single-plane chunks) gives the same step."""
+    n, nu = 17, 0.01
+    f0 = synth.random_populations(n, seed=300 + tile + chunk, amplitude=0.01)
+    if precision == "fp32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    with dhit.Box(n, "dugks", precision, nu, tile_width=tile, z_chunk=chunk) as box:
+        box.set_populations(f0)
+        box.step(2)
+        got = box.get_populations()
+    ref = O.dugks_step(f0, nu=nu, nsteps=2)
+    assert rel_err(got, ref) <= (TOL64 if precision == "fp64" else 2 * TOL32)
