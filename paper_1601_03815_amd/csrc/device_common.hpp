@@ -137,14 +137,20 @@ __device__ __forceinline__ void sums_of_cell(Real drho, Real jx, Real jy, Real j
   v[4] += 0.5 * (x * x + y * y + z * z) * inv_rho0 * inv_rho0;
 }
 
-// Writes the block's five sums to partials laid out [5][nblocks].
-__device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], double *partials, int nblocks,
-                                                     int block) {
-  __shared__ double smem[kBlock / 64][kNumSums];
+// Writes the block's five sums to partials laid out [5][nblocks], using
+// smem (at least one row of five doubles per wavefront of the block) for
+// the reduction.
+__device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], double *partials, int nblocks, int block,
+                                                     double (*smem)[kNumSums]) {
   block_sum5(v, smem);
   if (threadIdx.x == 0) {
     static_for<kNumSums>([&](auto i) { partials[(int64_t)i * nblocks + block] = v[i]; });
   }
+}
+__device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], double *partials, int nblocks,
+                                                     int block) {
+  __shared__ double smem[kBlock / 64][kNumSums];
+  write_block_partials(v, partials, nblocks, block, smem);
 }
 
 // Flat-index offsets of the +-1 neighbours along one axis with periodic

@@ -1,4 +1,5 @@
-// DUGKS time step in one kernel (Sec. II.A), LDS-tiled, marching in z.
+// DUGKS time step in one kernel (Sec. II.A), marching in z with one plane
+// of cell data in LDS at a time.
 //
 // Arithmetic.  With B = fbar+ (the cell transform of f~), h = dt/2 and the
 // face distribution f_face = alpha fbar_face + beta f^eq_face, the update
@@ -21,19 +22,32 @@
 //      = a Pi(f~) + b (drho/3 I + j j / rho0),
 // so only 10 moment fields (not 19 populations) are read per face.
 //
-// Tiling.  A block of 32 x 8 threads owns 32 x 8 (x, y) columns, of which
-// the inner 30 x 6 are updated and the outer ring is the halo, and marches
-// over a chunk of z.  Each thread keeps the loads of its column's cell two
-// planes ahead in flight, computes moments, B and f~+ of the next plane and
-// writes the fields its neighbours need to LDS:
-//   group A, three-plane ring (z-1, z, z+1): B of the populations moving in
-//     z (q5, q6, q11..q18) and Jz, Pxz, Pyz, Pzz;
-//   group B, two-plane ring (z, z+1): B of q1..q4, q7..q10 and R0, Jx, Jy,
-//     Pxx, Pxy, Pyy.
-// The z-face below the centre plane is the z-face above the previous centre
-// and is carried in registers, so group B is never needed at z-1.
-// HBM traffic per updated cell: 19 loads + 19 stores, plus the halo ring
-// (a factor 256/180 on loads, mostly served by the caches).
+// Plane-by-plane evaluation.  Every term above is a sum of pieces that each
+// involve one z-plane only (a plane's own cell and its in-plane
+// neighbours).  When plane p is in LDS, each thread adds the pieces of
+// plane p to the three centres that use it:
+//   centre p-1 (p is its z+1 plane): the z+1 terms of the z-moving
+//     populations and the upper half of the face between p-1 and p;
+//   centre p: the in-plane terms of the populations and the lower half of
+//     the face between p and p+1;
+//   centre p+1 (p is its z-1 plane): the z-1 terms of the z-moving
+//     populations.
+// The x- and y-faces of centre p-1 are formed in the same iteration from
+// the moment fields of planes p-2, p-1 and p, after which centre p-1 is
+// complete and stored.  Between planes a thread carries the running
+// results of centres p and p+1 in registers.  LDS holds the populations of
+// plane p only, the in-plane moment fields (R0, Jx, Jy, Pxx, Pxy, Pyy) of
+// planes p-1 and p, and the fields the x/y-faces differentiate in z (Jz,
+// Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column
+// (320 B in double, 40 KB for a block of 128 columns), so that four blocks
+// share a compute unit.
+//
+// Tiling.  A block of W x 8 threads owns W x 8 (x, y) columns, of which
+// the inner (W-2) x 6 are updated and the outer ring is the halo, and
+// marches over a chunk of z.  HBM traffic per updated cell: 19 loads + 19
+// stores, plus the halo ring (loads only).  Blocks are numbered so that the
+// tiles one XCD (one L2) works on at a time are neighbours, whose halo
+// columns then come from that L2.
 #include "collision.hpp"
 
 namespace dhit {
@@ -47,43 +61,31 @@ struct Tile {
 
 // Field ids: 0..18 populations of B; moment fields after them.
 enum : int { kR0 = 19, kJx, kJy, kJz, kPxx, kPxy, kPxz, kPyy, kPyz, kPzz };
-constexpr int kNA = 14, kNB = 14;
 
-constexpr int a_index(int id) {
+// LDS buffers: populations (one plane) other than 0, 5, 6 (the rest
+// population has no stencil, q5 and q6 only use their own column); the
+// in-plane moment fields (two planes); the fields differentiated in z
+// across x/y-faces (three planes).
+constexpr int kNPop = 16, kNQ = 6, kNZ = 4;
+constexpr int kLdsValues = kNPop + 2 * kNQ + 3 * kNZ;  // per column
+constexpr int pop_index(int id) { return (id >= 1 && id <= 4) ? id - 1 : ((id >= 7 && id <= 18) ? id - 3 : -1); }
+constexpr int q_index(int id) {
   switch (id) {
-    case 5: return 0;
-    case 6: return 1;
-    case 11: return 2;
-    case 12: return 3;
-    case 13: return 4;
-    case 14: return 5;
-    case 15: return 6;
-    case 16: return 7;
-    case 17: return 8;
-    case 18: return 9;
-    case kJz: return 10;
-    case kPxz: return 11;
-    case kPyz: return 12;
-    case kPzz: return 13;
+    case kR0: return 0;
+    case kJx: return 1;
+    case kJy: return 2;
+    case kPxx: return 3;
+    case kPxy: return 4;
+    case kPyy: return 5;
   }
   return -1;
 }
-constexpr int b_index(int id) {
+constexpr int z_index(int id) {
   switch (id) {
-    case 1: return 0;
-    case 2: return 1;
-    case 3: return 2;
-    case 4: return 3;
-    case 7: return 4;
-    case 8: return 5;
-    case 9: return 6;
-    case 10: return 7;
-    case kR0: return 8;
-    case kJx: return 9;
-    case kJy: return 10;
-    case kPxx: return 11;
-    case kPxy: return 12;
-    case kPyy: return 13;
+    case kJz: return 0;
+    case kPxz: return 1;
+    case kPyz: return 2;
+    case kPzz: return 3;
   }
   return -1;
 }
@@ -92,62 +94,136 @@ constexpr int pid(int a, int b) {
   const int lo = a < b ? a : b, hi = a < b ? b : a;
   return lo == 0 ? (hi == 0 ? kPxx : (hi == 1 ? kPxy : kPxz)) : (lo == 1 ? (hi == 1 ? kPyy : kPyz) : kPzz);
 }
+// Position of a z-moving population among the ten (q5, q6, q11..q18).
+constexpr int zslot(int q) { return q == 5 ? 0 : (q == 6 ? 1 : q - 9); }
+constexpr bool is_diag_z(int q) { return q >= 11; }
 
-template <typename Real, int W>
-struct Ctx {
-  static constexpr int TX = Tile<W>::TX, NT = Tile<W>::NT;
-  const Real *A;  // [3][kNA][NT]
-  const Real *B;  // [2][kNB][NT]
-  int sa[3];      // A slots of planes centre-1, centre, centre+1
-  int sb[3];      // B slots of planes centre-1, centre, centre+1 (two are valid at a time)
-  int tid;
-  template <int ID, int DZ, int DX, int DY>
-  __device__ __forceinline__ Real at() const {
-    constexpr int ia = a_index(ID), ib = b_index(ID);
-    static_assert(ia >= 0 || ib >= 0, "unknown field");
-    const int idx = tid + DY * TX + DX;
-    if constexpr (ia >= 0)
-      return A[(sa[DZ + 1] * kNA + ia) * NT + idx];
-    else
-      return B[(sb[DZ + 1] * kNB + ib) * NT + idx];
-  }
-};
+// Compiler-only memory fence between the phases of a plane's work: LDS
+// values are re-read after it instead of being kept live in registers
+// across phases, which bounds register pressure.  No instruction is emitted.
+__device__ __forceinline__ void phase() { asm volatile("" ::: "memory"); }
 
 template <int T>
 struct Unit {
   static constexpr int x = T == 0, y = T == 1, z = T == 2;
 };
 
-// Face moments (drho_b, j_b) of the face between L = centre + (LX, LY, LZ)
-// and R = L + e_D.
-template <int D, int LX, int LY, int LZ, typename Real, int W>
-__device__ __forceinline__ void face_moments(const Ctx<Real, W> &c, Real h, Real &rho_b, Real (&jb)[3]) {
-  constexpr int RX = LX + Unit<D>::x, RY = LY + Unit<D>::y, RZ = LZ + Unit<D>::z;
-  Real tang = Real(0);
-  static_for<3>([&](auto t) {
-    if constexpr (t != D) {
-      constexpr int ex = Unit<t>::x, ey = Unit<t>::y, ez = Unit<t>::z;
-      tang += (c.template at<jid(t), LZ + ez, LX + ex, LY + ey>() - c.template at<jid(t), LZ - ez, LX - ex, LY - ey>()) +
-              (c.template at<jid(t), RZ + ez, RX + ex, RY + ey>() - c.template at<jid(t), RZ - ez, RX - ex, RY - ey>());
+// Reads of one plane: populations from P, in-plane moment fields from Q,
+// z-differentiated fields from Z (each offset to the thread's column; a
+// plane whose populations or Q fields are no longer held has null there).
+template <typename Real, int W>
+struct Plane {
+  const Real *P;
+  const Real *Q;
+  const Real *Z;
+  template <int ID, int DX, int DY>
+  __device__ __forceinline__ Real at() const {
+    constexpr int NT = Tile<W>::NT, off = DY * W + DX;
+    constexpr int ip = pop_index(ID), iq = q_index(ID), iz = z_index(ID);
+    static_assert(ip >= 0 || iq >= 0 || iz >= 0, "field not in LDS");
+    if constexpr (ip >= 0)
+      return P[ip * NT + off];
+    else if constexpr (iq >= 0)
+      return Q[iq * NT + off];
+    else
+      return Z[iz * NT + off];
+  }
+};
+
+// In-plane central difference of field ID along in-plane axis t (0 or 1)
+// at the column offset (DX, DY).
+template <int ID, int T, int DX, int DY, class P>
+__device__ __forceinline__ auto dif(const P &c) {
+  return c.template at<ID, DX + Unit<T>::x, DY + Unit<T>::y>() - c.template at<ID, DX - Unit<T>::x, DY - Unit<T>::y>();
+}
+
+// Reads gathered ahead of their use.  A computation written against a
+// plane is run twice: once on a Load view, which issues every LDS read the
+// computation makes (its arithmetic is discarded), then on a Use view, which
+// replays it on the gathered values.  All reads of a chunk of work are thus
+// in flight together and their latencies overlap, instead of one read being
+// waited for before the next is issued.
+constexpr int kNumIds = 29;
+template <typename Real>
+struct Gathered {
+  Real v[kNumIds][3][3];  // field id, dy + 1, dx + 1
+};
+template <typename Real, int W, bool kLoad>
+struct GView {
+  static constexpr bool use = !kLoad;
+  const Plane<Real, W> &src;
+  Gathered<Real> &g;
+  template <int ID, int DX, int DY>
+  __device__ __forceinline__ Real at() const {
+    if constexpr (kLoad) {
+      g.v[ID][DY + 1][DX + 1] = src.template at<ID, DX, DY>();
+      return Real(0);
+    } else {
+      return g.v[ID][DY + 1][DX + 1];
     }
-  });
-  const Real r0l = c.template at<kR0, LZ, LX, LY>(), r0r = c.template at<kR0, RZ, RX, RY>();
-  const Real jdl = c.template at<jid(D), LZ, LX, LY>(), jdr = c.template at<jid(D), RZ, RX, RY>();
-  rho_b = (r0l + Real(0.5) * (r0r - r0l)) - h * ((jdr - jdl) + Real(0.25) * tang);
+  }
+};
+// f(view0, view1) with views of planes c0 and c1; f must change state only
+// when view0.use is true.
+template <typename Real, int W, class F>
+__device__ __forceinline__ void gathered(const Plane<Real, W> &c0, const Plane<Real, W> &c1, F &&f) {
+  Gathered<Real> g0, g1;
+  f(GView<Real, W, true>{c0, g0}, GView<Real, W, true>{c1, g1});
+  __builtin_amdgcn_sched_barrier(0);
+  f(GView<Real, W, false>{c0, g0}, GView<Real, W, false>{c1, g1});
+  phase();
+}
+
+// In-plane part of the moments of the D-face (D = 0 or 1) between
+// L = (LX, LY) and R = L + e_D in the current plane: everything but the
+// z-tangential gradients.  Face moment of field pair (value field V,
+// normal-flux field N, in-plane tangential field T):
+//   V_L + (V_R - V_L)/2 - h [(N_R - N_L) + (T(L+e_t) - T(L-e_t) + T(R+e_t) - T(R-e_t))/4]
+template <int D, int LX, int LY, typename Real, class P>
+__device__ __forceinline__ void face_inplane(const P &c, Real h, Real (&m)[4]) {
+  constexpr int t = 1 - D;
+  constexpr int RX = LX + Unit<D>::x, RY = LY + Unit<D>::y;
+  {
+    const Real tang = dif<jid(t), t, LX, LY>(c) + dif<jid(t), t, RX, RY>(c);
+    const Real vl = c.template at<kR0, LX, LY>(), vr = c.template at<kR0, RX, RY>();
+    const Real nl = c.template at<jid(D), LX, LY>(), nr = c.template at<jid(D), RX, RY>();
+    m[0] = (vl + Real(0.5) * (vr - vl)) - h * ((nr - nl) + Real(0.25) * tang);
+  }
   static_for<3>([&](auto a) {
-    Real tg = Real(0);
-    static_for<3>([&](auto t) {
-      if constexpr (t != D) {
-        constexpr int ex = Unit<t>::x, ey = Unit<t>::y, ez = Unit<t>::z;
-        constexpr int P = pid(a, t);
-        tg += (c.template at<P, LZ + ez, LX + ex, LY + ey>() - c.template at<P, LZ - ez, LX - ex, LY - ey>()) +
-              (c.template at<P, RZ + ez, RX + ex, RY + ey>() - c.template at<P, RZ - ez, RX - ex, RY - ey>());
-      }
-    });
-    constexpr int PN = pid(a, D);
-    const Real jl = c.template at<jid(a), LZ, LX, LY>(), jr = c.template at<jid(a), RZ, RX, RY>();
-    const Real pl = c.template at<PN, LZ, LX, LY>(), pr = c.template at<PN, RZ, RX, RY>();
-    jb[a] = (jl + Real(0.5) * (jr - jl)) - h * ((pr - pl) + Real(0.25) * tg);
+    constexpr int PN = pid(a, D), PT = pid(a, t);
+    const Real tang = dif<PT, t, LX, LY>(c) + dif<PT, t, RX, RY>(c);
+    const Real vl = c.template at<jid(a), LX, LY>(), vr = c.template at<jid(a), RX, RY>();
+    const Real nl = c.template at<PN, LX, LY>(), nr = c.template at<PN, RX, RY>();
+    m[1 + a] = (vl + Real(0.5) * (vr - vl)) - h * ((nr - nl) + Real(0.25) * tang);
+  });
+}
+
+// z-tangential part of an x/y-face moment pair sum: for the face between
+// L = (LX, LY) and R, the fields (Jz, Pxz, Pyz, Pzz) summed over L and R.
+template <int D, int LX, int LY, typename Real, class P>
+__device__ __forceinline__ void face_zsum(const P &c, Real (&s)[4]) {
+  constexpr int RX = LX + Unit<D>::x, RY = LY + Unit<D>::y;
+  s[0] = c.template at<kJz, LX, LY>() + c.template at<kJz, RX, RY>();
+  s[1] = c.template at<kPxz, LX, LY>() + c.template at<kPxz, RX, RY>();
+  s[2] = c.template at<kPyz, LX, LY>() + c.template at<kPyz, RX, RY>();
+  s[3] = c.template at<kPzz, LX, LY>() + c.template at<kPzz, RX, RY>();
+}
+
+// Half of the moments of a z-face that comes from one plane (the cell of
+// the column and its in-plane neighbours).  For the plane below the face
+// (S = +1) and the plane above it (S = -1):
+//   R0/2 + S h Jz - h/4 (dJx/dx + dJy/dy) and, for component a,
+//   J_a/2 + S h P_az - h/4 (dP_ax/dx + dP_ay/dy)   (central differences).
+template <int S, typename Real, class P>
+__device__ __forceinline__ void zface_half(const P &c, Real h, Real (&m)[4]) {
+  {
+    const Real tang = dif<kJx, 0, 0, 0>(c) + dif<kJy, 1, 0, 0>(c);
+    m[0] = Real(0.5) * c.template at<kR0, 0, 0>() + Real(S) * h * c.template at<kJz, 0, 0>() - Real(0.25) * h * tang;
+  }
+  static_for<3>([&](auto a) {
+    const Real tang = dif<pid(a, 0), 0, 0, 0>(c) + dif<pid(a, 1), 1, 0, 0>(c);
+    m[1 + a] = Real(0.5) * c.template at<jid(a), 0, 0>() + Real(S) * h * c.template at<pid(a, 2), 0, 0>() -
+               Real(0.25) * h * tang;
   });
 }
 
@@ -158,27 +234,23 @@ constexpr int pop_of(int x, int y, int z) {
   return -1;
 }
 
-// acc_q -= dt beta S xi_qD f^eq_q(face) for the ten populations crossing a
-// D-face (the face-equilibrium part of the flux difference, subtracted from
-// f~+ as each face is evaluated).  With u = j_b/rho0 and
-// f^eq_q = W_q [rho_b - 3/2 rho0 |u|^2 + 3 rho0 (xi.u) + 9/2 rho0 (xi.u)^2],
-// opposite velocities share the even part and flip the odd part, so each
-// pair is formed from one even and one odd term.
-template <int D, int S, typename Real>
-__device__ __forceinline__ void sub_face_equilibrium(Real rho_b, const Real (&jb)[3], const StepParams &p, Real dtbe,
-                                                     Real (&acc)[kQ]) {
+// Face-equilibrium terms of a D-face: calls put(q, v) for the ten
+// populations crossing it, v = dt beta xi_qD f^eq_q(face).  With
+// u = j_b/rho0 and f^eq_q = W_q [rho_b - 3/2 rho0 |u|^2 + 3 rho0 (xi.u)
+// + 9/2 rho0 (xi.u)^2], opposite velocities share the even part and flip
+// the odd part, so each pair is formed from one even and one odd term.
+template <int D, typename Real, class Put>
+__device__ __forceinline__ void face_equilibrium(const Real (&m)[4], const StepParams &p, Real dtbe, Put &&put) {
   const Real rho0 = Real(p.rho0), ir = Real(p.inv_rho0);
-  const Real u[3] = {jb[0] * ir, jb[1] * ir, jb[2] * ir};
-  const Real base = rho_b - Real(1.5) * rho0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const Real u[3] = {m[1] * ir, m[2] * ir, m[3] * ir};
+  const Real base = m[0] - Real(1.5) * rho0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const Real c3 = Real(3) * rho0, c45 = Real(4.5) * rho0;
-  const Real k1 = Real(S) * dtbe * Real(1.0 / 18.0), k2 = Real(S) * dtbe * Real(1.0 / 36.0);
+  const Real k1 = dtbe * Real(1.0 / 18.0), k2 = dtbe * Real(1.0 / 36.0);
   const Real ud = u[D];
   {
     const Real ev = base + c45 * ud * ud, od = c3 * ud;
-    constexpr int qp = pop_of(Unit<D>::x, Unit<D>::y, Unit<D>::z);
-    constexpr int qm = pop_of(-Unit<D>::x, -Unit<D>::y, -Unit<D>::z);
-    acc[qp] -= k1 * (ev + od);   // xi_D = +1
-    acc[qm] += k1 * (ev - od);   // xi_D = -1
+    put(std::integral_constant<int, pop_of(Unit<D>::x, Unit<D>::y, Unit<D>::z)>{}, k1 * (ev + od));
+    put(std::integral_constant<int, pop_of(-Unit<D>::x, -Unit<D>::y, -Unit<D>::z)>{}, -(k1 * (ev - od)));
   }
   static_for<3>([&](auto t) {
     if constexpr (t != D) {
@@ -188,69 +260,47 @@ __device__ __forceinline__ void sub_face_equilibrium(Real rho_b, const Real (&jb
       const Real em = base + c45 * um * um, om = c3 * um;
       constexpr int x = Unit<D>::x, y = Unit<D>::y, z = Unit<D>::z;
       constexpr int tx = Unit<t>::x, ty = Unit<t>::y, tz = Unit<t>::z;
-      constexpr int q_pp = pop_of(x + tx, y + ty, z + tz);      // xi.u = ud + ut
-      constexpr int q_pm = pop_of(x - tx, y - ty, z - tz);      // xi.u = ud - ut
-      constexpr int q_mp = pop_of(-x + tx, -y + ty, -z + tz);   // xi.u = -(ud - ut)
-      constexpr int q_mm = pop_of(-x - tx, -y - ty, -z - tz);   // xi.u = -(ud + ut)
-      acc[q_pp] -= k2 * (ep + op);
-      acc[q_pm] -= k2 * (em + om);
-      acc[q_mp] += k2 * (em - om);
-      acc[q_mm] += k2 * (ep - op);
+      put(std::integral_constant<int, pop_of(x + tx, y + ty, z + tz)>{}, k2 * (ep + op));      // xi.u = ud + ut
+      put(std::integral_constant<int, pop_of(x - tx, y - ty, z - tz)>{}, k2 * (em + om));      // xi.u = ud - ut
+      put(std::integral_constant<int, pop_of(-x + tx, -y + ty, -z + tz)>{}, -(k2 * (em - om)));  // -(ud - ut)
+      put(std::integral_constant<int, pop_of(-x - tx, -y - ty, -z - tz)>{}, -(k2 * (ep - op)));  // -(ud + ut)
     }
   });
 }
 
-// Linear part L_q of the flux difference (stencil of B_q).
-template <int Q, typename Real, int W>
-__device__ __forceinline__ Real linear_part(const Ctx<Real, W> &c, Real h) {
-  constexpr int sx = kCx[Q], sy = kCy[Q], sz = kCz[Q];
-  constexpr int nz = (sx != 0) + (sy != 0) + (sz != 0);
-  const Real b0 = c.template at<Q, 0, 0, 0>();
-  if constexpr (nz == 1) {
-    constexpr int ex = sx != 0, ey = sy != 0, ez = sz != 0;
-    constexpr int s = sx + sy + sz;
-    const Real bp = c.template at<Q, ez, ex, ey>(), bm = c.template at<Q, -ez, -ex, -ey>();
-    return Real(0.5 * s) * (bp - bm) - h * ((bp + bm) - Real(2) * b0);
-  } else {
-    // the two nonzero directions d1 < d2 with signs s1, s2
-    constexpr int d1 = sx != 0 ? 0 : 1;
-    constexpr int d2 = sz != 0 ? 2 : 1;
-    constexpr int s1 = cdir(Q, d1), s2 = cdir(Q, d2);
-    constexpr int x1 = Unit<d1>::x, y1 = Unit<d1>::y, z1 = Unit<d1>::z;
-    constexpr int x2 = Unit<d2>::x, y2 = Unit<d2>::y, z2 = Unit<d2>::z;
-    const Real p1 = c.template at<Q, z1, x1, y1>(), m1 = c.template at<Q, -z1, -x1, -y1>();
-    const Real p2 = c.template at<Q, z2, x2, y2>(), m2 = c.template at<Q, -z2, -x2, -y2>();
-    const Real pp = c.template at<Q, z1 + z2, x1 + x2, y1 + y2>();
-    const Real pm = c.template at<Q, z1 - z2, x1 - x2, y1 - y2>();
-    const Real mp = c.template at<Q, -z1 + z2, -x1 + x2, -y1 + y2>();
-    const Real mm = c.template at<Q, -z1 - z2, -x1 - x2, -y1 - y2>();
-    return (Real(0.5 * s1) * (p1 - m1) + Real(0.5 * s2) * (p2 - m2)) -
-           h * (((p1 + m1) + (p2 + m2)) - Real(4) * b0) - Real(0.5 * s1 * s2) * h * (((pp - pm) - mp) + mm);
-  }
+// acc_q -= S v_q for the populations crossing a D-face of the centre
+// (S = +1 for its upper face, -1 for its lower face).
+template <int D, int S, typename Real>
+__device__ __forceinline__ void sub_face(const Real (&m)[4], const StepParams &p, Real dtbe, Real (&acc)[kQ]) {
+  face_equilibrium<D, Real>(m, p, dtbe, [&](auto q, Real v) {
+    if constexpr (S > 0)
+      acc[q] -= v;
+    else
+      acc[q] += v;
+  });
 }
 
 // Issues the loads of the 19 f~ of the column's cell in plane `plane`
-// (periodic in z).  The values are consumed one loop iteration later, so the
-// loads overlap the work on the centre plane.
+// (periodic in z).
 template <typename Real>
 __device__ __forceinline__ void load_raw(const Real *__restrict__ ft, int64_t stride, int n, int col, int plane,
                                          Real (&f)[kQ]) {
   const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
-  const int cell = z * n * n + col;
-  static_for<kQ>([&](auto q) { f[q] = ft[(int64_t)q * stride + cell]; });
+  const Real *base = ft + (int64_t)z * n * n;
+  static_for<kQ>([&](auto q) { f[q] = base[(int64_t)q * stride + col]; });
 }
 
-// From the 19 f~ of a cell: moments, B = a f~ + b f^eq, the moment fields of
-// B; writes the fields its neighbours need to the LDS slots (sa, sb) and
-// returns f~+ = 4/3 B - 1/3 f~.
-template <typename Real, int W>
-__device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb, Real *A, Real *B, int tid,
-                                             const StepParams &p, Real (&ftp)[kQ]) {
+// From the 19 f~ of a cell: moments, B = a f~ + b f^eq and f~+ =
+// 4/3 B - 1/3 f~, and the moment fields of B; writes the fields other
+// columns read to the plane's LDS buffers P, Q, Z (offset to the thread's
+// column) and hands each population's (B, f~+) to
+// use(q, B_q, f~+_q) as soon as it is formed.
+template <typename Real, int W, class Use>
+__device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real *Q, Real *Z, const StepParams &p,
+                                             Use &&use) {
   constexpr int NT = Tile<W>::NT;
-  Real drho, jx, jy, jz, feq[kQ];
+  Real drho, jx, jy, jz;
   cell_moments<Real>(f, drho, jx, jy, jz);
-  equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
-  // second moments of f~
   Real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
   static_for<kQ>([&](auto q) {
     constexpr int x = kCx[q], y = kCy[q], z = kCz[q];
@@ -264,46 +314,55 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], int sa, int sb
     if constexpr (y * z == 1) pyz += f[q];
     if constexpr (y * z == -1) pyz -= f[q];
   });
+  const Real rho0 = Real(p.rho0), ir = Real(p.inv_rho0);
+  const Real a = Real(p.a_bp);
+  const Real d3 = drho * Real(1.0 / 3.0);
+  // P = a Pi(f~) + b Pi(f^eq), Pi(f^eq) = drho/3 I + j j / rho0, formed as
+  // Pi(f^eq) + a (Pi(f~) - Pi(f^eq)) (see below)
+  {
+    const Real exx = d3 + jx * jx * ir, eyy = d3 + jy * jy * ir, ezz = d3 + jz * jz * ir;
+    const Real exy = jx * jy * ir, exz = jx * jz * ir, eyz = jy * jz * ir;
+    Q[q_index(kR0) * NT] = drho;
+    Q[q_index(kJx) * NT] = jx;
+    Q[q_index(kJy) * NT] = jy;
+    Q[q_index(kPxx) * NT] = exx + a * (pxx - exx);
+    Q[q_index(kPxy) * NT] = exy + a * (pxy - exy);
+    Q[q_index(kPyy) * NT] = eyy + a * (pyy - eyy);
+    Z[z_index(kJz) * NT] = jz;
+    Z[z_index(kPxz) * NT] = exz + a * (pxz - exz);
+    Z[z_index(kPyz) * NT] = eyz + a * (pyz - eyz);
+    Z[z_index(kPzz) * NT] = ezz + a * (pzz - ezz);
+  }
   // B = a f~ + b f^eq with a + b = 1 is formed as f^eq + a (f~ - f^eq) and
   // f~+ = 4/3 B - 1/3 f~ as B + (B - f~)/3, so that an equilibrium cell maps
   // to itself exactly in any precision (rounded 4/3 and 1/3, or a and b,
-  // would otherwise scale the state by 1 + O(ulp) every step)
-  const Real a = Real(p.a_bp);
-  const Real ir = Real(p.inv_rho0);
-  const Real d3 = drho * Real(1.0 / 3.0);
-  Real fld[29];
+  // would otherwise scale the state by 1 + O(ulp) every step).  f^eq is the
+  // equilibrium of Sec. II.A, as in equilibrium().
+  const Real ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const Real base = drho - Real(1.5) * rho0 * (ux * ux + uy * uy + uz * uz);
   static_for<kQ>([&](auto q) {
-    const Real bp = feq[q] + a * (f[q] - feq[q]);
-    fld[q] = bp;
-    ftp[q] = bp + (bp - f[q]) * Real(1.0 / 3.0);
-  });
-  fld[kR0] = drho;
-  fld[kJx] = jx;
-  fld[kJy] = jy;
-  fld[kJz] = jz;
-  // P = a Pi(f~) + b Pi(f^eq), Pi(f^eq) = drho/3 I + j j / rho0, in the same form
-  const Real exx = d3 + jx * jx * ir, eyy = d3 + jy * jy * ir, ezz = d3 + jz * jz * ir;
-  const Real exy = jx * jy * ir, exz = jx * jz * ir, eyz = jy * jz * ir;
-  fld[kPxx] = exx + a * (pxx - exx);
-  fld[kPyy] = eyy + a * (pyy - eyy);
-  fld[kPzz] = ezz + a * (pzz - ezz);
-  fld[kPxy] = exy + a * (pxy - exy);
-  fld[kPxz] = exz + a * (pxz - exz);
-  fld[kPyz] = eyz + a * (pyz - eyz);
-  static_for<29>([&](auto id) {
-    constexpr int ia = a_index(id), ib = b_index(id);
-    if constexpr (ia >= 0) A[(sa * kNA + ia) * NT + tid] = fld[id];
-    if constexpr (ib >= 0) B[(sb * kNB + ib) * NT + tid] = fld[id];
+    constexpr Real w = Real(kWeight(q));
+    Real xu = Real(0);
+    if constexpr (kCx[q] == 1) xu += ux;
+    if constexpr (kCx[q] == -1) xu -= ux;
+    if constexpr (kCy[q] == 1) xu += uy;
+    if constexpr (kCy[q] == -1) xu -= uy;
+    if constexpr (kCz[q] == 1) xu += uz;
+    if constexpr (kCz[q] == -1) xu -= uz;
+    const Real feq = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
+    const Real b = feq + a * (f[q] - feq);
+    if constexpr (pop_index(q) >= 0) P[pop_index(q) * NT] = b;
+    use(q, b, b + (b - f[q]) * Real(1.0 / 3.0));
   });
 }
 
 // The z-march of one tile (bx, by) over the z-chunk bz of a box; adds the
-// moments of the updated cells to v.  A and B are the block's LDS rings.
+// moments of the updated cells to v.  L is the block's LDS, kLdsValues
+// values per column: P [kNPop][NT], Q [2][kNQ][NT], Z [3][kNZ][NT].
 template <typename Real, int W>
 __device__ __forceinline__ void fused_tile(const Real *__restrict__ ft, Real *__restrict__ out, const StepParams &p,
-                                           int bx, int by, int bz, int nz_chunk, Real *A, Real *B,
-                                           double (&v)[kNumSums]) {
-  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY;
+                                           int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
+  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   const int n = p.n;
   const int64_t stride = p.stride;
   const int tid = threadIdx.x;
@@ -317,82 +376,200 @@ __device__ __forceinline__ void fused_tile(const Real *__restrict__ ft, Real *__
   const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
   const Real h = Real(p.h), dt = Real(p.dt);
   const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
+  Real *const LP = L + tid;
+  Real *const LQ = L + kNPop * NT + tid;
+  Real *const LZ = L + (kNPop + 2 * kNQ) * NT + tid;
 
-  auto slot3 = [](int z) { return (z + 3) % 3; };
-  auto slot2 = [](int z) { return (z + 2) % 2; };
+  Real pf[kQ];        // f~ of the plane being published (loaded one plane ahead)
+  Real acc_c[kQ];     // result of centre p-1, completed in this iteration
+  Real acc_p[kQ];     // result of centre p
+  Real nxt[10];       // z-1 terms of the z-moving populations of centre p+1
+  Real zl[4];         // lower half of the z-face above the previous plane
+  static_for<kQ>([&](auto q) { acc_p[q] = Real(0); });
+  static_for<10>([&](auto i) { nxt[i] = Real(0); });
+  static_for<4>([&](auto i) { zl[i] = Real(0); });
 
-  Real pf[kQ], acc[kQ], ftp_next[kQ];
-  Real rho_zm = Real(0), jzm[3] = {Real(0), Real(0), Real(0)};
-
-  // prologue: planes z0-1 and z0 published, plane z0+1 in flight, and the
-  // z-face between z0-1 and z0
   load_raw<Real>(ft, stride, n, col, z0 - 1, pf);
-  publish_cell<Real, W>(pf, slot3(z0 - 1), slot2(z0 - 1), A, B, tid, p, acc);
-  load_raw<Real>(ft, stride, n, col, z0, pf);
-  publish_cell<Real, W>(pf, slot3(z0), slot2(z0), A, B, tid, p, acc);
-  load_raw<Real>(ft, stride, n, col, z0 + 1, pf);
-  __syncthreads();
-  {
-    Ctx<Real, W> c{A, B, {slot3(z0 - 1), slot3(z0), slot3(z0 + 1)}, {slot2(z0 - 1), slot2(z0), slot2(z0 + 1)}, tid};
-    if (inner && z0 < z1) face_moments<2, 0, 0, -1, Real>(c, h, rho_zm, jzm);
-  }
-  __syncthreads();
+  int q2 = 0, q3 = 0;  // Q slot and Z slot of plane p
+  for (int p_ = z0 - 1; p_ <= z1; ++p_) {
+    const bool has_prev = p_ > z0;          // centre p-1 is in the chunk
+    const bool has_cur = p_ >= z0 && p_ < z1;
+    const int q2m = q2 ^ 1, q3m = q3 == 0 ? 2 : q3 - 1, q3mm = q3 == 2 ? 0 : q3 + 1;
+    const Plane<Real, W> c{LP, LQ + q2 * (kNQ * NT), LZ + q3 * (kNZ * NT)};        // plane p
+    const Plane<Real, W> c1{nullptr, LQ + q2m * (kNQ * NT), LZ + q3m * (kNZ * NT)};  // plane p-1
+    const Plane<Real, W> c2{nullptr, nullptr, LZ + q3mm * (kNZ * NT)};              // plane p-2
 
-  for (int z = z0; z < z1; ++z) {
-    // acc holds f~+ of the centre plane z; publish plane z+1, prefetch z+2
-    publish_cell<Real, W>(pf, slot3(z + 1), slot2(z + 1), A, B, tid, p, ftp_next);
-    if (z + 1 < z1) load_raw<Real>(ft, stride, n, col, z + 2, pf);
+    // centre p-1 becomes the completed centre
+    static_for<kQ>([&](auto q) { acc_c[q] = acc_p[q]; });
+    // own-column pieces of plane p: z+1 terms of centre p-1, the centre
+    // terms and initial value of centre p, z-1 terms of centre p+1 (formed
+    // by halo columns too, which never store them)
+    publish_cell<Real, W>(pf, LP, LQ + q2 * (kNQ * NT), LZ + q3 * (kNZ * NT), p, [&](auto q, Real bq, Real ftq) {
+      if constexpr (kCz[q] != 0) acc_c[q] -= dtal * ((Real(0.5 * kCz[q]) - h) * bq);
+      Real r = ftq;
+      if constexpr (kCz[q] != 0) r += nxt[zslot(q)];
+      if constexpr (q != 0) r -= dtal * (Real(speed2(q) == 1 ? 2 : 4) * h * bq);
+      acc_p[q] = r;
+      if constexpr (kCz[q] != 0) nxt[zslot(q)] = -(dtal * ((Real(-0.5 * kCz[q]) - h) * bq));
+    });
     __syncthreads();
+
     if (inner) {
-      Ctx<Real, W> c{A, B, {slot3(z - 1), slot3(z), slot3(z + 1)}, {slot2(z - 1), slot2(z), slot2(z + 1)}, tid};
-      {
-        Real rb, jb[3];
-        face_moments<0, 0, 0, 0, Real>(c, h, rb, jb);
-        sub_face_equilibrium<0, 1, Real>(rb, jb, p, dtbe, acc);
-        face_moments<0, -1, 0, 0, Real>(c, h, rb, jb);
-        sub_face_equilibrium<0, -1, Real>(rb, jb, p, dtbe, acc);
-        face_moments<1, 0, 0, 0, Real>(c, h, rb, jb);
-        sub_face_equilibrium<1, 1, Real>(rb, jb, p, dtbe, acc);
-        face_moments<1, 0, -1, 0, Real>(c, h, rb, jb);
-        sub_face_equilibrium<1, -1, Real>(rb, jb, p, dtbe, acc);
-        sub_face_equilibrium<2, -1, Real>(rho_zm, jzm, p, dtbe, acc);
-        face_moments<2, 0, 0, 0, Real>(c, h, rho_zm, jzm);  // the z-face above, carried to the next plane
-        sub_face_equilibrium<2, 1, Real>(rho_zm, jzm, p, dtbe, acc);
-      }
-      static_for<kQ>([&](auto q) {
-        if constexpr (q != 0) acc[q] -= dtal * linear_part<q, Real>(c, h);
+      // face between p-1 and p (upper half from plane p, lower half carried
+      // from plane p-1) and the lower half of the face between p and p+1
+      gathered<Real, W>(c, c, [&](const auto &g, const auto &) {
+        Real m[4], lo[4];
+        zface_half<-1>(g, h, m);
+        zface_half<1>(g, h, lo);
+        if constexpr (std::decay_t<decltype(g)>::use) {
+          static_for<4>([&](auto i) { m[i] += zl[i]; });
+          face_equilibrium<2, Real>(m, p, dtbe, [&](auto q, Real val) {
+            acc_c[q] -= val;   // upper face of centre p-1
+            acc_p[q] += val;   // lower face of centre p
+          });
+          static_for<4>([&](auto i) { zl[i] = lo[i]; });
+        }
       });
-      const int cell = z * n * n + col;
-      static_for<kQ>([&](auto q) { __builtin_nontemporal_store(acc[q], &out[(int64_t)q * stride + cell]); });
-      sums_of_populations<Real>(acc, p.inv_rho0, v);
+      // diagonal z-moving populations: the in-plane differences D = B(+d1)
+      // - B(-d1) and sums S = B(+d1) + B(-d1) of plane p enter centre p-1
+      // (z+1 mixed term), centre p (in-plane terms) and centre p+1 (z-1
+      // mixed term)
+      gathered<Real, W>(c, c, [&](const auto &g, const auto &) {
+        static_for<kQ>([&](auto q) {
+          if constexpr (is_diag_z(q)) {
+            constexpr int d1 = kCx[q] != 0 ? 0 : 1, s1 = kCx[q] + kCy[q];
+            constexpr Real k = Real(0.5 * s1 * kCz[q]);
+            const Real bp_ = g.template at<q, Unit<d1>::x, Unit<d1>::y>();
+            const Real bm_ = g.template at<q, -Unit<d1>::x, -Unit<d1>::y>();
+            if constexpr (std::decay_t<decltype(g)>::use) {
+              const Real dd = bp_ - bm_;
+              acc_c[q] += dtal * (k * h * dd);
+              acc_p[q] -= dtal * (Real(0.5 * s1) * dd - h * (bp_ + bm_));
+              nxt[zslot(q)] -= dtal * (k * h * dd);
+            }
+          }
+        });
+      });
+      if (has_prev) {
+        // x- and y-faces of centre p-1: in-plane part from plane p-1, the
+        // z-tangential gradients -h/4 [(M_L + M_R)(p) - (M_L + M_R)(p-2)]
+        const Real hq = Real(0.25) * h;
+        auto xy_face = [&](auto D, auto LX, auto LY, auto S) {
+          Real m[4];
+          gathered<Real, W>(c1, c1, [&](const auto &g, const auto &) {
+            Real t[4];
+            face_inplane<D, LX, LY>(g, h, t);
+            if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { m[i] = t[i]; });
+          });
+          gathered<Real, W>(c, c2, [&](const auto &g, const auto &g2) {
+            Real s1[4], s0[4];
+            face_zsum<D, LX, LY>(g, s1);
+            face_zsum<D, LX, LY>(g2, s0);
+            if constexpr (std::decay_t<decltype(g)>::use) {
+              static_for<4>([&](auto i) { m[i] -= hq * (s1[i] - s0[i]); });
+              sub_face<D, S, Real>(m, p, dtbe, acc_c);
+            }
+          });
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using Im1 = std::integral_constant<int, -1>;
+        xy_face(I0{}, I0{}, I0{}, I1{});     // x+
+        xy_face(I0{}, Im1{}, I0{}, Im1{});   // x-
+        xy_face(I1{}, I0{}, I0{}, I1{});     // y+
+        xy_face(I1{}, I0{}, Im1{}, Im1{});   // y-
+        const int cell = (p_ - 1) * n * n + col;
+        static_for<kQ>([&](auto q) { __builtin_nontemporal_store(acc_c[q], &out[(int64_t)q * stride + cell]); });
+        sums_of_populations<Real>(acc_c, p.inv_rho0, v);
+      }
     }
-    static_for<kQ>([&](auto q) { acc[q] = ftp_next[q]; });
+    phase();
+    // loads of the next plane overlap the rest of this one
+    if (p_ < z1) load_raw<Real>(ft, stride, n, col, p_ + 1, pf);
+
+    if (inner && has_cur) {
+      // in-plane terms of the in-plane populations of centre p (the centre
+      // value was added before)
+      //   axis: L = s/2 (B(+d) - B(-d)) - h (B(+d) + B(-d))
+      gathered<Real, W>(c, c, [&](const auto &g, const auto &) {
+        static_for<5>([&](auto q) {
+          if constexpr (q >= 1) {
+            constexpr int d = kCx[q] != 0 ? 0 : 1, s = kCx[q] + kCy[q];
+            const Real bp_ = g.template at<q, Unit<d>::x, Unit<d>::y>();
+            const Real bm_ = g.template at<q, -Unit<d>::x, -Unit<d>::y>();
+            if constexpr (std::decay_t<decltype(g)>::use)
+              acc_p[q] -= dtal * (Real(0.5 * s) * (bp_ - bm_) - h * (bp_ + bm_));
+          }
+        });
+      });
+      //   diagonal in the plane, in the (x, y) frame of its own signs
+      auto diag_xy = [&](auto q, const auto &g) {
+        constexpr int sx = kCx[q], sy = kCy[q];
+        const Real p1 = g.template at<q, 1, 0>(), m1 = g.template at<q, -1, 0>();
+        const Real p2 = g.template at<q, 0, 1>(), m2 = g.template at<q, 0, -1>();
+        const Real pp = g.template at<q, sx, sy>(), pm = g.template at<q, sx, -sy>();
+        const Real mp = g.template at<q, -sx, sy>(), mm = g.template at<q, -sx, -sy>();
+        if constexpr (std::decay_t<decltype(g)>::use) {
+          const Real a1 = sx > 0 ? (p1 - m1) : (m1 - p1);
+          const Real a2 = sy > 0 ? (p2 - m2) : (m2 - p2);
+          acc_p[q] -= dtal * ((Real(0.5) * a1 + Real(0.5) * a2) - h * ((p1 + m1) + (p2 + m2)) -
+                              Real(0.5) * h * (((pp - pm) - mp) + mm));
+        }
+      };
+      gathered<Real, W>(c, c, [&](const auto &g, const auto &) {
+        diag_xy(std::integral_constant<int, 7>{}, g);
+        diag_xy(std::integral_constant<int, 8>{}, g);
+      });
+      gathered<Real, W>(c, c, [&](const auto &g, const auto &) {
+        diag_xy(std::integral_constant<int, 9>{}, g);
+        diag_xy(std::integral_constant<int, 10>{}, g);
+      });
+    }
+    q2 ^= 1;
+    q3 = q3 == 2 ? 0 : q3 + 1;
     __syncthreads();
   }
 }
 
+// Register budget: FP32 tiles are held to 256 registers (two waves per
+// SIMD); the FP64 march needs more, and runs one wave per SIMD.
+template <typename Real>
+constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
+
+// Tile of a block, numbered so that the blocks one XCD runs (blocks are
+// dealt to the eight XCDs in turn) take consecutive tiles: block b of a
+// launch of `padded` blocks (a multiple of 8) takes tile
+// (b mod 8) * padded/8 + b/8.
+__device__ __forceinline__ int xcd_tile(int b, int padded) { return (b & 7) * (padded >> 3) + (b >> 3); }
+
 template <typename Real, int W>
-__global__ __launch_bounds__(Tile<W>::NT) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
+__global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
                                                                   StepParams p, int tiles_x, int tiles_y,
-                                                                  int nz_chunk, double *__restrict__ partials) {
-  __shared__ Real A[3 * kNA * Tile<W>::NT];
-  __shared__ Real B[2 * kNB * Tile<W>::NT];
-  const int bx = blockIdx.x % tiles_x;
-  const int by = (blockIdx.x / tiles_x) % tiles_y;
-  const int bz = blockIdx.x / (tiles_x * tiles_y);
+                                                                  int nz_chunk, int ntiles, double *__restrict__ partials) {
+  __shared__ Real L[kLdsValues * Tile<W>::NT];
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const int bx = t % tiles_x;
+  const int by = (t / tiles_x) % tiles_y;
+  const int bz = t / (tiles_x * tiles_y);
   double v[kNumSums] = {0, 0, 0, 0, 0};
-  fused_tile<Real, W>(ft, out, p, bx, by, bz, nz_chunk, A, B, v);
-  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+  fused_tile<Real, W>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+  // the march ends with a barrier: L is free for the block reduction
+  write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
 }
 
 // Many boxes in one persistent launch: work item = one tile z-chunk of one
-// box, numbered as the blocks of that box's single-box launch.
+// box, numbered as the tiles of that box's single-box launch.  Round r of
+// the grid takes items [r G, (r+1) G), dealt to the XCDs in contiguous
+// eighths.
 template <typename Real, int W>
-__global__ __launch_bounds__(Tile<W>::NT) void dugks_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
+__global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
                                                                   int total_items) {
-  __shared__ Real A[3 * kNA * Tile<W>::NT];
-  __shared__ Real B[2 * kNB * Tile<W>::NT];
-  for (int it = blockIdx.x; it < total_items; it += gridDim.x) {
+  __shared__ Real L[kLdsValues * Tile<W>::NT];
+  const int G = gridDim.x;
+  for (int base = 0; base < total_items; base += G) {
+    const int it = base + xcd_tile(blockIdx.x, G);
+    if (it >= total_items) continue;
     const int b = find_batch_box(boxes, nbox, it);
     const BatchBox &d = boxes[b];
     const int local = it - d.item_begin;
@@ -401,16 +578,16 @@ __global__ __launch_bounds__(Tile<W>::NT) void dugks_batch_kernel(BatchBox *__re
     const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
     fused_tile<Real, W>(static_cast<const Real *>(d.f[d.cur]), static_cast<Real *>(d.f[d.cur ^ 1]), d.sp, bx, by, bz,
-                        d.nz_chunk, A, B, v);
-    write_block_partials(v, d.partials, d.items, local);
+                        d.nz_chunk, L, v);
+    write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
   }
 }
 
 }  // namespace fused
 
-// Default tile width by precision: FP64 tiles of 16 x 8 columns use 72 KB of
-// LDS, so two blocks share a compute unit; FP32 tiles of 32 x 8 use 72 KB too.
+// Default tile width by precision: 16 x 8 columns (FP64) and 32 x 8 (FP32),
+// both 40 KB of LDS per block.
 constexpr int fused_tile_width(int precision) { return precision == DHIT_FP64 ? 16 : 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
@@ -424,7 +601,8 @@ int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_
   return tx * ty * ((n + chunk - 1) / chunk);
 }
 
-// Blocks of a single-box fused launch with the box's tile width and z-chunk.
+// Tiles of a single-box fused launch with the box's tile width and z-chunk
+// (one block per tile; the grid is rounded up to a multiple of 8).
 int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
   const int n = p.n;
   const int w = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
@@ -441,30 +619,32 @@ int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tile
 }
 
 template <typename Real, int W>
-static void fused_launch(dhit_box &b, const void *src, void *dst, int blocks, int tx, int ty, int cz) {
-  hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(blocks), dim3(fused::Tile<W>::NT), 0, b.stream,
-                     static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, b.partials);
+static void fused_launch(dhit_box &b, const void *src, void *dst, int tiles, int tx, int ty, int cz) {
+  const int grid = (tiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, b.stream,
+                     static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
 }
 
 template <typename Real>
 static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
   int w, tx, ty, cz;
-  const int blocks = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
+  const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
     if (w == 16)
-      fused_launch<Real, 16>(b, src, dst, blocks, tx, ty, cz);
+      fused_launch<Real, 16>(b, src, dst, tiles, tx, ty, cz);
     else
-      fused_launch<Real, 32>(b, src, dst, blocks, tx, ty, cz);
+      fused_launch<Real, 32>(b, src, dst, tiles, tx, ty, cz);
     DHIT_HIP(hipGetLastError());
     t.done();
   }
-  launch_finalize_sums(b, b.partials, blocks, sums_out);
+  launch_finalize_sums(b, b.partials, tiles, sums_out);
 }
 
 int fused_tile_width_of(int precision) { return fused_tile_width(precision); }
 
 void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid) {
+  grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8
   if (precision == DHIT_FP64) {
     constexpr int W = fused_tile_width(DHIT_FP64);
     hipLaunchKernelGGL((fused::dugks_batch_kernel<double, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
