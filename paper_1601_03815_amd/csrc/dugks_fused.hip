@@ -584,6 +584,433 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Split-population march.  Two thread groups share each column of the
+// tile: group A (the first NT threads) holds the ten z-moving populations
+// (5, 6, 11..18), group B the other nine.  Each step is done by one group:
+// A the z-moving stencils and the x-face moments, B the in-plane stencils,
+// the z-face and y-face moments and the global sums; each applies the face
+// equilibria to its own populations.  The groups exchange the partial
+// moment sums of each published cell, the face moments and A's part of the
+// stored cells' sums through LDS.  A thread carries the state of about half
+// a column, so each compute unit holds twice the waves of the
+// one-thread-per-column march.
+constexpr int kPopsA[10] = {5, 6, 11, 12, 13, 14, 15, 16, 17, 18};
+constexpr int kPopsB[9] = {0, 1, 2, 3, 4, 7, 8, 9, 10};
+template <int G>
+struct Group {
+  static constexpr int N = G == 0 ? 10 : 9;
+  static constexpr int pop(int i) { return G == 0 ? kPopsA[i] : kPopsB[i]; }
+};
+constexpr int group_of(int q) { return (q == 5 || q == 6 || q >= 11) ? 0 : 1; }
+constexpr int local_of(int q) {
+  for (int i = 0; i < 10; ++i)
+    if (kPopsA[i] == q) return i;
+  for (int i = 0; i < 9; ++i)
+    if (kPopsB[i] == q) return i;
+  return -1;
+}
+// LDS per column after the plane buffers:
+//   RA [12]: A's partial moments (read by B after the first barrier of an
+//            iteration), then the y-face moments [0..8) and the z-face
+//            moments [8..12) formed by B (read by A after the third);
+//   RB [10]: B's partial moments, then the x-face moments [0..8) formed by A;
+//   SA [4]:  A's part of the sums of its last stored cell (read by B in the
+//            next iteration).
+// Every reuse is separated from the previous reads by a barrier or by
+// program order within the one thread of the column that does both.
+constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10;
+constexpr int kSplitValues = kSA + 4;
+
+// Loads of the group's populations of the column's cell in plane `plane`.
+template <typename Real, int G>
+__device__ __forceinline__ void load_group(const Real *__restrict__ ft, int64_t stride, int n, int col, int plane,
+                                           Real (&f)[Group<G>::N]) {
+  const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
+  const Real *base = ft + (int64_t)z * n * n;
+  static_for<Group<G>::N>([&](auto i) { f[i] = base[(int64_t)Group<G>::pop(i) * stride + col]; });
+}
+
+// Partial moment sums over the group's populations: drho, jx, jy, jz,
+// Pi_xx, Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz (compensated in FP32 for drho
+// and j, as cell_moments()).
+template <typename Real, int G>
+__device__ __forceinline__ void partial_moments(const Real (&f)[Group<G>::N], Real (&m)[10]) {
+  CompSum<Real> r, ax, ay, az;
+  Real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+  static_for<Group<G>::N>([&](auto i) {
+    constexpr int q = Group<G>::pop(i);
+    constexpr int x = kCx[q], y = kCy[q], z = kCz[q];
+    const Real v = f[i];
+    if constexpr (std::is_same<Real, double>::value) {
+      r.s += v;
+      if constexpr (x != 0) ax.s += Real(x) * v;
+      if constexpr (y != 0) ay.s += Real(y) * v;
+      if constexpr (z != 0) az.s += Real(z) * v;
+    } else {
+      r.add(v);
+      if constexpr (x == 1) ax.add(v);
+      if constexpr (x == -1) ax.sub(v);
+      if constexpr (y == 1) ay.add(v);
+      if constexpr (y == -1) ay.sub(v);
+      if constexpr (z == 1) az.add(v);
+      if constexpr (z == -1) az.sub(v);
+    }
+    if constexpr (x != 0) pxx += v;
+    if constexpr (y != 0) pyy += v;
+    if constexpr (z != 0) pzz += v;
+    if constexpr (x * y == 1) pxy += v;
+    if constexpr (x * y == -1) pxy -= v;
+    if constexpr (x * z == 1) pxz += v;
+    if constexpr (x * z == -1) pxz -= v;
+    if constexpr (y * z == 1) pyz += v;
+    if constexpr (y * z == -1) pyz -= v;
+  });
+  m[0] = r.value(); m[1] = ax.value(); m[2] = ay.value(); m[3] = az.value();
+  m[4] = pxx; m[5] = pyy; m[6] = pzz; m[7] = pxy; m[8] = pxz; m[9] = pyz;
+}
+
+// The rest of publishing a cell, from its full moment sums m: B and f~+ of
+// the group's populations (handed to use(q, B_q, f~+_q)), their LDS
+// entries, and the group's moment fields (A: Jz, Pxz, Pyz, Pzz; B: R0, Jx,
+// Jy, Pxx, Pxy, Pyy), in the equilibrium-exact forms of publish_cell().
+template <typename Real, int W, int G, class Use>
+__device__ __forceinline__ void publish_group(const Real (&f)[Group<G>::N], const Real (&m)[10], Real *P, Real *Q,
+                                              Real *Z, const StepParams &p, Use &&use) {
+  constexpr int NT = Tile<W>::NT;
+  const Real drho = m[0], jx = m[1], jy = m[2], jz = m[3];
+  const Real rho0 = Real(p.rho0), ir = Real(p.inv_rho0);
+  const Real a = Real(p.a_bp);
+  const Real d3 = drho * Real(1.0 / 3.0);
+  if constexpr (G == 0) {
+    const Real ezz = d3 + jz * jz * ir, exz = jx * jz * ir, eyz = jy * jz * ir;
+    Z[z_index(kJz) * NT] = jz;
+    Z[z_index(kPxz) * NT] = exz + a * (m[8] - exz);
+    Z[z_index(kPyz) * NT] = eyz + a * (m[9] - eyz);
+    Z[z_index(kPzz) * NT] = ezz + a * (m[6] - ezz);
+  } else {
+    const Real exx = d3 + jx * jx * ir, eyy = d3 + jy * jy * ir, exy = jx * jy * ir;
+    Q[q_index(kR0) * NT] = drho;
+    Q[q_index(kJx) * NT] = jx;
+    Q[q_index(kJy) * NT] = jy;
+    Q[q_index(kPxx) * NT] = exx + a * (m[4] - exx);
+    Q[q_index(kPxy) * NT] = exy + a * (m[7] - exy);
+    Q[q_index(kPyy) * NT] = eyy + a * (m[5] - eyy);
+  }
+  const Real ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const Real base = drho - Real(1.5) * rho0 * (ux * ux + uy * uy + uz * uz);
+  static_for<Group<G>::N>([&](auto i) {
+    constexpr int q = Group<G>::pop(i);
+    constexpr Real w = Real(kWeight(q));
+    Real xu = Real(0);
+    if constexpr (kCx[q] == 1) xu += ux;
+    if constexpr (kCx[q] == -1) xu -= ux;
+    if constexpr (kCy[q] == 1) xu += uy;
+    if constexpr (kCy[q] == -1) xu -= uy;
+    if constexpr (kCz[q] == 1) xu += uz;
+    if constexpr (kCz[q] == -1) xu -= uz;
+    const Real feq = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
+    const Real b = feq + a * (f[i] - feq);
+    if constexpr (pop_index(q) >= 0) P[pop_index(q) * NT] = b;
+    use(std::integral_constant<int, q>{}, b, b + (b - f[i]) * Real(1.0 / 3.0));
+  });
+}
+
+// The z-march of group G of a tile (see above).  L: the block's LDS,
+// kSplitValues values per column.
+template <typename Real, int W, int G>
+__device__ __forceinline__ void split_tile(const Real *__restrict__ ft, Real *__restrict__ out, const StepParams &p,
+                                           int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
+  constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
+  constexpr int NG = Group<G>::N;
+  const int n = p.n;
+  const int64_t stride = p.stride;
+  const int c = threadIdx.x - G * NT;  // column of the tile
+  const int tx = c % TX, ty = c / TX;
+  const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
+  const int z1 = min(z0 + nz_chunk, n);
+  int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
+  gx = gx < 0 ? gx + n : (gx >= n ? gx % n : gx);
+  gy = gy < 0 ? gy + n : (gy >= n ? gy % n : gy);
+  const int col = gy * n + gx;
+  const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
+  const Real h = Real(p.h), dt = Real(p.dt);
+  const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
+  const double ir = p.inv_rho0;
+  Real *const LP = L + c;
+  Real *const LQ = L + kNPop * NT + c;
+  Real *const LZ = L + (kNPop + 2 * kNQ) * NT + c;
+  Real *const RA = L + kRA * NT + c;
+  Real *const RB = L + kRB * NT + c;
+  Real *const SA = L + kSA * NT + c;
+
+  Real pf[NG];            // the group's f~ of the plane being published
+  Real acc_c[NG];         // centre p-1
+  Real acc_p[NG];         // centre p
+  Real nxt[10];           // A: z-1 terms of centre p+1 (all of A's populations move in z)
+  Real zl[4];             // B: lower half of the z-face above the previous plane
+  double jb[3] = {0, 0, 0};  // B: its part of the momentum of the last stored cell
+  static_for<NG>([&](auto i) { acc_p[i] = Real(0); });
+  static_for<10>([&](auto i) { nxt[i] = Real(0); });
+  static_for<4>([&](auto i) { zl[i] = Real(0); });
+
+  load_group<Real, G>(ft, stride, n, col, z0 - 1, pf);
+  int q2 = 0, q3 = 0;
+  for (int p_ = z0 - 1; p_ <= z1; ++p_) {
+    const bool has_prev = p_ > z0;
+    const bool has_cur = p_ >= z0 && p_ < z1;
+    const bool stored_last = p_ - 1 > z0;  // a cell was stored in the previous iteration
+    const int q2m = q2 ^ 1, q3m = q3 == 0 ? 2 : q3 - 1, q3mm = q3 == 2 ? 0 : q3 + 1;
+    const Plane<Real, W> pc{LP, LQ + q2 * (kNQ * NT), LZ + q3 * (kNZ * NT)};
+    const Plane<Real, W> pc1{nullptr, LQ + q2m * (kNQ * NT), LZ + q3m * (kNZ * NT)};
+    const Plane<Real, W> pc2{nullptr, nullptr, LZ + q3mm * (kNZ * NT)};
+
+    static_for<NG>([&](auto i) { acc_c[i] = acc_p[i]; });
+    // partial moments of this group's populations, exchanged with the other group
+    Real m[10];
+    partial_moments<Real, G>(pf, m);
+    static_for<10>([&](auto k) { (G == 0 ? RA : RB)[k * NT] = m[k]; });
+    __syncthreads();
+    static_for<10>([&](auto k) { m[k] = G == 0 ? m[k] + RB[k * NT] : RA[k * NT] + m[k]; });
+    if constexpr (G == 1) {
+      if (inner && stored_last) {
+        const double ra = (double)SA[0], xa = (double)SA[NT], ya = (double)SA[2 * NT], za = (double)SA[3 * NT];
+        v[0] += ra; v[1] += xa; v[2] += ya; v[3] += za;
+        const double x = jb[0] + xa, y = jb[1] + ya, z = jb[2] + za;
+        v[4] += 0.5 * (x * x + y * y + z * z) * ir * ir;
+      }
+    }
+    // own-column pieces of plane p (see fused_tile)
+    publish_group<Real, W, G>(pf, m, LP, LQ + q2 * (kNQ * NT), LZ + q3 * (kNZ * NT), p, [&](auto q, Real bq, Real ftq) {
+      constexpr int i = local_of(q);
+      if constexpr (kCz[q] != 0) acc_c[i] -= dtal * ((Real(0.5 * kCz[q]) - h) * bq);
+      Real r = ftq;
+      if constexpr (kCz[q] != 0) r += nxt[i];
+      if constexpr (q != 0) r -= dtal * (Real(speed2(q) == 1 ? 2 : 4) * h * bq);
+      acc_p[i] = r;
+      if constexpr (kCz[q] != 0) nxt[i] = -(dtal * ((Real(-0.5 * kCz[q]) - h) * bq));
+    });
+    __syncthreads();
+
+    Real fx[2][4];  // the faces this group forms: A x+ and x-, B y+ and y-
+    if (inner) {
+      if constexpr (G == 0) {
+        // diagonal z-moving populations: in-plane differences D = B(+d1) -
+        // B(-d1) and sums S = B(+d1) + B(-d1) of plane p enter centre p-1
+        // (z+1 mixed term), centre p (in-plane terms), centre p+1 (z-1 mixed term)
+        gathered<Real, W>(pc, pc, [&](const auto &g, const auto &) {
+          static_for<kQ>([&](auto q) {
+            if constexpr (is_diag_z(q)) {
+              constexpr int d1 = kCx[q] != 0 ? 0 : 1, s1 = kCx[q] + kCy[q];
+              constexpr Real k = Real(0.5 * s1 * kCz[q]);
+              constexpr int i = local_of(q);
+              const Real bp_ = g.template at<q, Unit<d1>::x, Unit<d1>::y>();
+              const Real bm_ = g.template at<q, -Unit<d1>::x, -Unit<d1>::y>();
+              if constexpr (std::decay_t<decltype(g)>::use) {
+                const Real dd = bp_ - bm_;
+                acc_c[i] += dtal * (k * h * dd);
+                acc_p[i] -= dtal * (Real(0.5 * s1) * dd - h * (bp_ + bm_));
+                nxt[i] -= dtal * (k * h * dd);
+              }
+            }
+          });
+        });
+      } else {
+        // face between p-1 and p (upper half from plane p, lower half
+        // carried from plane p-1) for A, and the lower half of the next one
+        gathered<Real, W>(pc, pc, [&](const auto &g, const auto &) {
+          Real mm[4], lo[4];
+          zface_half<-1>(g, h, mm);
+          zface_half<1>(g, h, lo);
+          if constexpr (std::decay_t<decltype(g)>::use) {
+            static_for<4>([&](auto i) { RA[(8 + i) * NT] = mm[i] + zl[i]; });
+            static_for<4>([&](auto i) { zl[i] = lo[i]; });
+          }
+        });
+        if (has_cur) {
+          gathered<Real, W>(pc, pc, [&](const auto &g, const auto &) {
+            static_for<5>([&](auto q) {
+              if constexpr (q >= 1) {
+                constexpr int d = kCx[q] != 0 ? 0 : 1, s = kCx[q] + kCy[q];
+                const Real bp_ = g.template at<q, Unit<d>::x, Unit<d>::y>();
+                const Real bm_ = g.template at<q, -Unit<d>::x, -Unit<d>::y>();
+                if constexpr (std::decay_t<decltype(g)>::use)
+                  acc_p[local_of(q)] -= dtal * (Real(0.5 * s) * (bp_ - bm_) - h * (bp_ + bm_));
+              }
+            });
+          });
+          auto diag_xy = [&](auto q, const auto &g) {
+            constexpr int sx = kCx[q], sy = kCy[q];
+            const Real p1 = g.template at<q, 1, 0>(), m1 = g.template at<q, -1, 0>();
+            const Real p2 = g.template at<q, 0, 1>(), m2 = g.template at<q, 0, -1>();
+            const Real pp = g.template at<q, sx, sy>(), pm = g.template at<q, sx, -sy>();
+            const Real mp = g.template at<q, -sx, sy>(), mm = g.template at<q, -sx, -sy>();
+            if constexpr (std::decay_t<decltype(g)>::use) {
+              const Real a1 = sx > 0 ? (p1 - m1) : (m1 - p1);
+              const Real a2 = sy > 0 ? (p2 - m2) : (m2 - p2);
+              acc_p[local_of(q)] -= dtal * ((Real(0.5) * a1 + Real(0.5) * a2) - h * ((p1 + m1) + (p2 + m2)) -
+                                            Real(0.5) * h * (((pp - pm) - mp) + mm));
+            }
+          };
+          gathered<Real, W>(pc, pc, [&](const auto &g, const auto &) {
+            diag_xy(std::integral_constant<int, 7>{}, g);
+            diag_xy(std::integral_constant<int, 8>{}, g);
+          });
+          gathered<Real, W>(pc, pc, [&](const auto &g, const auto &) {
+            diag_xy(std::integral_constant<int, 9>{}, g);
+            diag_xy(std::integral_constant<int, 10>{}, g);
+          });
+        }
+      }
+      if (has_prev) {
+        // the group's two faces of centre p-1: in-plane part from plane
+        // p-1, z-tangential gradients -h/4 [(M_L + M_R)(p) - (M_L + M_R)(p-2)];
+        // written for the other group (A's into RB, B's into RA)
+        constexpr int D = G == 0 ? 0 : 1;
+        const Real hq = Real(0.25) * h;
+        auto face = [&](auto LX, auto LY, Real (&fm)[4]) {
+          gathered<Real, W>(pc1, pc1, [&](const auto &g, const auto &) {
+            Real t[4];
+            face_inplane<D, LX, LY>(g, h, t);
+            if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { fm[i] = t[i]; });
+          });
+          gathered<Real, W>(pc, pc2, [&](const auto &g, const auto &g2) {
+            Real s1[4], s0[4];
+            face_zsum<D, LX, LY>(g, s1);
+            face_zsum<D, LX, LY>(g2, s0);
+            if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { fm[i] -= hq * (s1[i] - s0[i]); });
+          });
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using Im1 = std::integral_constant<int, -1>;
+        face(I0{}, I0{}, fx[0]);                        // upper face
+        if constexpr (G == 0) face(Im1{}, I0{}, fx[1]);  // x-
+        else face(I0{}, Im1{}, fx[1]);                   // y-
+        static_for<2>([&](auto f) { static_for<4>([&](auto i) { (G == 0 ? RB : RA)[(f * 4 + i) * NT] = fx[f][i]; }); });
+      }
+    }
+    phase();
+    if (p_ < z1) load_group<Real, G>(ft, stride, n, col, p_ + 1, pf);
+    if (p_ >= z0) {
+      __syncthreads();
+      if (inner) {
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        auto put_face = [&](const Real (&fm)[4], auto D, auto S) {
+          face_equilibrium<D, Real>(fm, p, dtbe, [&](auto q, Real val) {
+            if constexpr (group_of(q) == G) {
+              if constexpr (S > 0)
+                acc_c[local_of(q)] -= val;
+              else
+                acc_c[local_of(q)] += val;
+            }
+          });
+        };
+        if constexpr (G == 0) {
+          // the z-face between p-1 and p: upper face of centre p-1, lower of centre p
+          Real zf[4];
+          static_for<4>([&](auto i) { zf[i] = RA[(8 + i) * NT]; });
+          face_equilibrium<2, Real>(zf, p, dtbe, [&](auto q, Real val) {
+            acc_c[local_of(q)] -= val;
+            acc_p[local_of(q)] += val;
+          });
+        }
+        if (has_prev) {
+          // equilibrium parts of the four x/y-faces of centre p-1 for this
+          // group's populations: its own two faces and the other group's
+          Real fo[2][4];
+          static_for<2>([&](auto f) { static_for<4>([&](auto i) { fo[f][i] = (G == 0 ? RA : RB)[(f * 4 + i) * NT]; }); });
+          using Ip = std::integral_constant<int, 1>;
+          using Im = std::integral_constant<int, -1>;
+          if constexpr (G == 0) {
+            put_face(fx[0], I0{}, Ip{}); put_face(fx[1], I0{}, Im{});
+            put_face(fo[0], I1{}, Ip{}); put_face(fo[1], I1{}, Im{});
+          } else {
+            put_face(fo[0], I0{}, Ip{}); put_face(fo[1], I0{}, Im{});
+            put_face(fx[0], I1{}, Ip{}); put_face(fx[1], I1{}, Im{});
+          }
+          const int cell = (p_ - 1) * n * n + col;
+          double r = 0, ax = 0, ay = 0, az = 0;
+          static_for<NG>([&](auto i) {
+            constexpr int q = Group<G>::pop(i);
+            __builtin_nontemporal_store(acc_c[i], &out[(int64_t)q * stride + cell]);
+            const double x = (double)acc_c[i];
+            r += x;
+            if constexpr (kCx[q] != 0) ax += kCx[q] * x;
+            if constexpr (kCy[q] != 0) ay += kCy[q] * x;
+            if constexpr (kCz[q] != 0) az += kCz[q] * x;
+          });
+          if constexpr (G == 0) {
+            SA[0] = Real(r); SA[NT] = Real(ax); SA[2 * NT] = Real(ay); SA[3 * NT] = Real(az);
+          } else {
+            v[0] += r; v[1] += ax; v[2] += ay; v[3] += az;
+            jb[0] = ax; jb[1] = ay; jb[2] = az;
+          }
+        }
+      }
+    }
+    q2 ^= 1;
+    q3 = q3 == 2 ? 0 : q3 + 1;
+  }
+  // A's part of the sums of the last stored cell
+  __syncthreads();
+  if constexpr (G == 1) {
+    if (inner) {
+      const double ra = (double)SA[0], xa = (double)SA[NT], ya = (double)SA[2 * NT], za = (double)SA[3 * NT];
+      v[0] += ra; v[1] += xa; v[2] += ya; v[3] += za;
+      const double x = jb[0] + xa, y = jb[1] + ya, z = jb[2] + za;
+      v[4] += 0.5 * (x * x + y * y + z * z) * ir * ir;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename Real, int W>
+__global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const Real *__restrict__ ft,
+                                                                      Real *__restrict__ out, StepParams p,
+                                                                      int tiles_x, int tiles_y, int nz_chunk,
+                                                                      int ntiles, double *__restrict__ partials) {
+  __shared__ Real L[kSplitValues * Tile<W>::NT];
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const int bx = t % tiles_x;
+  const int by = (t / tiles_x) % tiles_y;
+  const int bz = t / (tiles_x * tiles_y);
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  if (threadIdx.x < Tile<W>::NT)
+    split_tile<Real, W, 0>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+  else
+    split_tile<Real, W, 1>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+  write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
+}
+
+template <typename Real, int W>
+__global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
+                                                                            int total_items) {
+  __shared__ Real L[kSplitValues * Tile<W>::NT];
+  const int G = gridDim.x;
+  for (int base = 0; base < total_items; base += G) {
+    const int it = base + xcd_tile(blockIdx.x, G);
+    if (it >= total_items) continue;
+    const int b = find_batch_box(boxes, nbox, it);
+    const BatchBox &d = boxes[b];
+    const int local = it - d.item_begin;
+    const int bx = local % d.tiles_x;
+    const int by = (local / d.tiles_x) % d.tiles_y;
+    const int bz = local / (d.tiles_x * d.tiles_y);
+    double v[kNumSums] = {0, 0, 0, 0, 0};
+    const Real *src = static_cast<const Real *>(d.f[d.cur]);
+    Real *dst = static_cast<Real *>(d.f[d.cur ^ 1]);
+    if (threadIdx.x < Tile<W>::NT)
+      split_tile<Real, W, 0>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
+    else
+      split_tile<Real, W, 1>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
+    write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
+    __syncthreads();
+  }
+}
+
 }  // namespace fused
 
 // Default tile width by precision: 16 x 8 columns (FP64) and 32 x 8 (FP32),
@@ -618,11 +1045,20 @@ int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tile
   return tx * ty * nzc;
 }
 
+// FP64 tiles use the split-population march (two thread groups per
+// column), FP32 tiles one thread per column.
+template <typename Real>
+constexpr bool kSplit = sizeof(Real) == 8;
+
 template <typename Real, int W>
 static void fused_launch(dhit_box &b, const void *src, void *dst, int tiles, int tx, int ty, int cz) {
   const int grid = (tiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, b.stream,
-                     static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
+  if constexpr (kSplit<Real>)
+    hipLaunchKernelGGL((fused::dugks_split_kernel<Real, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, b.stream,
+                       static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
+  else
+    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, b.stream,
+                       static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
 }
 
 template <typename Real>
@@ -647,8 +1083,8 @@ void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbo
   grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8
   if (precision == DHIT_FP64) {
     constexpr int W = fused_tile_width(DHIT_FP64);
-    hipLaunchKernelGGL((fused::dugks_batch_kernel<double, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
-                       nbox, total_items);
+    hipLaunchKernelGGL((fused::dugks_split_batch_kernel<double, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, s,
+                       d_boxes, nbox, total_items);
   } else {
     constexpr int W = fused_tile_width(DHIT_FP32);
     hipLaunchKernelGGL((fused::dugks_batch_kernel<float, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
