@@ -78,7 +78,7 @@ typedef struct dhit_params {
     int32_t precision;  /* enum dhit_precision */
     int32_t variant;    /* enum dhit_variant */
     int32_t tile_width; /* fused DUGKS kernel: width of a block's column tile, 16 or 32
-                           (0 = the default for the precision: 16 for FP64, 32 for FP32) */
+                           (0 = the default, 32) */
     int32_t z_chunk;    /* fused DUGKS kernel: planes one block marches through,
                            0 = default (32 for n >= 128, 16 for n >= 32, else n) */
     double nu;          /* kinematic viscosity, > 0 */

@@ -1013,9 +1013,10 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
 
 }  // namespace fused
 
-// Default tile width by precision: 16 x 8 columns (FP64) and 32 x 8 (FP32),
-// both 40 KB of LDS per block.
-constexpr int fused_tile_width(int precision) { return precision == DHIT_FP64 ? 16 : 32; }
+// Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
+// FP64 (split march, 512 threads): 132 KB of LDS, one block per compute
+// unit; FP32 (256 threads): 40 KB, four blocks per compute unit.
+constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
 
