@@ -153,6 +153,7 @@ def extras(torch, dhit):
         trace = serve.poisson_trace(count, 20.0, seed=7)
         be = serve.GpuBackend(precision="fp32", nu=0.01)
         st = serve.Scheduler(be, budget, max_active=64, chunk=64).run(trace)
+        be.close()
         st["offered_rate_per_s"] = 20.0
         srv[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         torch.cuda.empty_cache()

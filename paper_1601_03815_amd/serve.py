@@ -15,6 +15,9 @@ latency from arrival to result is recorded.
 The scheduler talks to a backend object (GPU: `GpuBackend`; tests use a fake
 one) with these methods:
     bytes_of(req) -> int       device bytes the run needs while active
+    prepare(req)               optional: called once when the request arrives,
+                               before admission (the GPU backend starts
+                               generating its initial field in the background)
     start(req) -> handle       allocate and initialise the run
     advance(handles, nsteps)   advance active runs (all of one method) by nsteps
     finish(handle) -> result   final diagnostics of a finished run
@@ -80,6 +83,16 @@ class Scheduler:
         self.peak_in_use = 0
         self.active = []
         self.results = {}
+        self._prepared = set()
+
+    def _prepare(self, waiting, now):
+        prep = getattr(self.backend, "prepare", None)
+        if prep is None:
+            return
+        for req in waiting:
+            if req.arrival <= now and req.rid not in self._prepared:
+                self._prepared.add(req.rid)
+                prep(req)
 
     def _admit(self, waiting, now):
         admitted = []
@@ -106,6 +119,7 @@ class Scheduler:
         cells_steps = 0
         while waiting or self.active:
             now = clock() - t0
+            self._prepare(waiting, now)
             self._admit(waiting, now)
             if not self.active:
                 if waiting:
@@ -145,9 +159,13 @@ class Scheduler:
 
 class GpuBackend:
     """Runs requests as library boxes on the current GPU: FP32 by default,
-    one PyTorch stream per method, one batch per method and chunk."""
+    one PyTorch stream per method, one batch per method and chunk.  Initial
+    fields are generated on host threads from the request's arrival on, so
+    that admission does not wait for them."""
 
-    def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None):
+    def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None, field_workers=4):
+        import concurrent.futures
+
         import torch
 
         from . import Batch, Box, box_bytes, default_params
@@ -161,6 +179,12 @@ class GpuBackend:
             import synth
             fields = lambda req: synth.dhit_field(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
         self.fields = fields
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=field_workers)
+        self._pending = {}   # rid -> future of the initial field
+
+    def prepare(self, req):
+        if req.rid not in self._pending:
+            self._pending[req.rid] = self._pool.submit(self.fields, req)
 
     def _stream(self, method):
         if method not in self.streams:
@@ -174,8 +198,10 @@ class GpuBackend:
         return self._box_bytes(p) + 64 * req.n ** 3
 
     def start(self, req):
+        fut = self._pending.pop(req.rid, None)
+        u = fut.result() if fut is not None else self.fields(req)
         b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._stream(req.method))
-        b.init_velocity_field(self.fields(req))
+        b.init_velocity_field(u)
         return b
 
     def advance(self, boxes, nsteps):
@@ -207,3 +233,7 @@ class GpuBackend:
             bt.close()
         self.batches = {}
         self._torch.cuda.synchronize()
+
+    def close(self):
+        self._pool.shutdown(wait=True)
+        self._pending = {}

@@ -100,6 +100,33 @@ def test_scheduler_rejects_oversized_request():
         sch.run([Request(0.0, 0, 64, "mrt", 10, 1)], clock=clock, sleep=clock.sleep)
 
 
+def test_prepare_is_called_once_per_request_after_arrival_before_start():
+    """A backend's prepare hook (initial-field generation ahead of admission)
+    sees every request once, no earlier than its arrival and before start."""
+    clock = FakeClock()
+
+    class PreparingBackend(FakeBackend):
+        def __init__(self, clock):
+            super().__init__(clock, rate=1e6)
+            self.prepared = {}
+
+        def prepare(self, req):
+            assert req.rid not in self.prepared
+            assert clock() >= req.arrival
+            self.prepared[req.rid] = clock()
+
+        def start(self, req):
+            assert req.rid in self.prepared
+            return super().start(req)
+
+    be = PreparingBackend(clock)
+    trace = poisson_trace(30, 50.0, seed=5, grids=(16, 32), weights=(1, 1), steps=(50, 200))
+    sch = Scheduler(be, 40 * 2 * 8 * 19 * 32 ** 3, max_active=4, chunk=25)
+    sch.run(trace, clock=clock, sleep=clock.sleep)
+    assert sorted(be.prepared) == sorted(r.rid for r in trace)
+    assert len(sch.results) == len(trace)
+
+
 @pytest.mark.gpu
 def test_result_is_the_same_alone_and_in_the_mix():
     """Runs served together (continuous batching, both methods overlapping on
@@ -115,6 +142,7 @@ def test_result_is_the_same_alone_and_in_the_mix():
     be = GpuBackend(precision="fp32", nu=0.01)
     sch = Scheduler(be, 4e9, chunk=16)
     stats = sch.run(trace)
+    be.close()
     assert stats["requests"] == len(trace)
     for r in trace:
         with dhit.Box(r.n, r.method, "fp32", 0.01) as b:
