@@ -46,8 +46,8 @@ def kernel_source_hash(kernel):
              "dugks_transform": ["dugks.hip", "device_common.hpp", "lattice.hpp"],
              "dugks_fused": ["dugks_fused.hip", "collision.hpp", "device_common.hpp", "lattice.hpp"]}.get(kernel, [])
     h = hashlib.sha256()
-    for f in files:
-        p = os.path.join(csrc, f)
+    # the build script's flags shape the machine code too
+    for p in [os.path.join(csrc, f) for f in files] + [os.path.join(ROOT, "paper_1601_03815_amd", "build.py")]:
         if os.path.exists(p):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
