@@ -13,20 +13,22 @@ constexpr int kBlock = 256;            // threads per block of the streaming ker
 constexpr int kWaves = kBlock / 64;    // 64-wide wavefronts per block
 constexpr int kNumSums = 5;            // sum drho, sum jx, sum jy, sum jz, 1/2 sum |u|^2
 
-// Compensated summation (Knuth's TwoSum) used for the per-cell moment sums
-// of FP32 boxes: s + c carries the sum with the rounding error of every
-// addition accumulated in c.
+// Compensated summation (Kahan): s carries the running sum and c the
+// rounding error of the last addition (with its sign reversed), which is
+// fed back into the next term, so that the error of a sum of m terms stays
+// O(eps) instead of O(m eps).  Used for the per-cell moment sums of FP32
+// boxes.
 template <typename Real>
 struct CompSum {
   Real s = Real(0), c = Real(0);
   __device__ __forceinline__ void add(Real x) {
-    Real t = s + x;
-    Real z = t - s;
-    c += (s - (t - z)) + (x - z);
+    const Real y = x - c;
+    const Real t = s + y;
+    c = (t - s) - y;
     s = t;
   }
   __device__ __forceinline__ void sub(Real x) { add(-x); }
-  __device__ __forceinline__ Real value() const { return s + c; }
+  __device__ __forceinline__ Real value() const { return s - c; }
 };
 
 // Moments of one cell: drho = sum f, j = sum xi f (Sec. II.A / II.B).
