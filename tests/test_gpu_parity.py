@@ -217,6 +217,27 @@ def test_full_size_sampled_cells_fp64(method, n):
     assert rel_err(got[:, cells].T, ref) <= TOL64
 
 
+@pytest.mark.parametrize("method", ["mrt", "dugks"])
+@pytest.mark.parametrize("n", [128, 256])
+def test_full_size_sampled_cells_fp32(method, n):
+    """The FP32 deviation-form kernels at the benchmark's sizes and launch
+    configuration: one step from a random state (rounded to FP32 on both
+    sides), checked on sampled cells against the oracle's per-cell update."""
+    nu = 0.005 if n == 128 else 0.0025
+    print("full-size sampled fp32: %s n=%d" % (method, n), flush=True)
+    f0 = synth.random_populations(n, seed=7 + n, amplitude=0.01).astype(np.float32).astype(np.float64)
+    with dhit.Box(n, method, "fp32", nu) as box:
+        box.set_populations(f0)
+        box.step(1)
+        got = box.get_populations().reshape(Q, -1)
+    cells = _sample_cells(n, 3000, seed=n + 1)
+    if method == "dugks":
+        ref = O.dugks_cells(f0, cells, nu=nu)
+    else:
+        ref = O.lbe_pull_cells(f0, cells, method, nu)
+    assert rel_err(got[:, cells].T, ref) <= TOL32
+
+
 def test_step_method_mismatch_and_validation():
     with dhit.Box(4, "dugks", "fp64", 0.01) as box:
         with pytest.raises(dhit.DhitError) as e:
