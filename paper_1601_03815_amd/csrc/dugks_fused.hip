@@ -38,16 +38,22 @@
 // results of centres p and p+1 in registers.  LDS holds the populations of
 // plane p only, the in-plane moment fields (R0, Jx, Jy, Pxx, Pxy, Pyy) of
 // planes p-1 and p, and the fields the x/y-faces differentiate in z (Jz,
-// Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column
-// (320 B in double, 40 KB for a block of 128 columns), so that four blocks
-// share a compute unit.
+// Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column.
 //
-// Tiling.  A block of W x 8 threads owns W x 8 (x, y) columns, of which
-// the inner (W-2) x 6 are updated and the outer ring is the halo, and
-// marches over a chunk of z.  HBM traffic per updated cell: 19 loads + 19
-// stores, plus the halo ring (loads only).  Blocks are numbered so that the
-// tiles one XCD (one L2) works on at a time are neighbours, whose halo
-// columns then come from that L2.
+// Two marches implement this.  fused_tile (FP32): one thread per column,
+// 40 values of LDS per column (40 KB for a 32 x 8 tile, four blocks per
+// compute unit).  split_tile (FP64): two threads per column, one in each of
+// two groups that hold about half of the populations each (see below), so
+// that a thread's registers fit two waves per SIMD; 66 values per column.
+// LDS reads are gathered (see gathered()) so that each chunk of work waits
+// for LDS once.
+//
+// Tiling.  A block owns W x 8 (x, y) columns, of which the inner (W-2) x 6
+// are updated and the outer ring is the halo, and marches over a chunk of
+// z.  HBM traffic per updated cell: 19 loads + 19 stores, plus the halo
+// ring (loads only).  Blocks are numbered so that the tiles one XCD (one L2)
+// works on at a time are neighbours, whose halo columns then come from that
+// L2.
 #include "collision.hpp"
 
 namespace dhit {
@@ -290,6 +296,49 @@ __device__ __forceinline__ void load_raw(const Real *__restrict__ ft, int64_t st
   static_for<kQ>([&](auto q) { f[q] = base[(int64_t)q * stride + col]; });
 }
 
+// The ten moments drho, j, Pi of a cell (or of the populations get(q)
+// yields for q in a set closed under q -> -q), formed from opposite-velocity
+// pairs: with s = f_q + f_-q and d = f_q - f_-q over the pairs (q < -q),
+//   drho = f_0 + sum s,  j = sum xi_q d,  Pi_ab = sum xi_qa xi_qb s.
+// FP32: drho and j are compensated sums over the pair terms.
+// m = {drho, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz}.
+template <typename Real, class Has, class Get>
+__device__ __forceinline__ void pair_moments(Has has, Get get, Real (&m)[10]) {
+  CompSum<Real> r, ax, ay, az;
+  Real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+  constexpr bool plain = std::is_same<Real, double>::value;
+  auto acc = [&](CompSum<Real> &c, Real x) {
+    if constexpr (plain)
+      c.s += x;
+    else
+      c.add(x);
+  };
+  if constexpr (has(0)) acc(r, get(std::integral_constant<int, 0>{}));
+  static_for<kQ>([&](auto q) {
+    constexpr int qb = opposite(q);
+    if constexpr (q != 0 && q < qb && has(q)) {
+      const Real fq = get(q), fb = get(std::integral_constant<int, qb>{});
+      const Real sm = fq + fb, df = fq - fb;
+      constexpr int x = kCx[q], y = kCy[q], z = kCz[q];
+      acc(r, sm);
+      if constexpr (x != 0) acc(ax, x > 0 ? df : -df);
+      if constexpr (y != 0) acc(ay, y > 0 ? df : -df);
+      if constexpr (z != 0) acc(az, z > 0 ? df : -df);
+      if constexpr (x != 0) pxx += sm;
+      if constexpr (y != 0) pyy += sm;
+      if constexpr (z != 0) pzz += sm;
+      if constexpr (x * y == 1) pxy += sm;
+      if constexpr (x * y == -1) pxy -= sm;
+      if constexpr (x * z == 1) pxz += sm;
+      if constexpr (x * z == -1) pxz -= sm;
+      if constexpr (y * z == 1) pyz += sm;
+      if constexpr (y * z == -1) pyz -= sm;
+    }
+  });
+  m[0] = r.value(); m[1] = ax.value(); m[2] = ay.value(); m[3] = az.value();
+  m[4] = pxx; m[5] = pyy; m[6] = pzz; m[7] = pxy; m[8] = pxz; m[9] = pyz;
+}
+
 // From the 19 f~ of a cell: moments, B = a f~ + b f^eq and f~+ =
 // 4/3 B - 1/3 f~, and the moment fields of B; writes the fields other
 // columns read to the plane's LDS buffers P, Q, Z (offset to the thread's
@@ -299,21 +348,10 @@ template <typename Real, int W, class Use>
 __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real *Q, Real *Z, const StepParams &p,
                                              Use &&use) {
   constexpr int NT = Tile<W>::NT;
-  Real drho, jx, jy, jz;
-  cell_moments<Real>(f, drho, jx, jy, jz);
-  Real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-  static_for<kQ>([&](auto q) {
-    constexpr int x = kCx[q], y = kCy[q], z = kCz[q];
-    if constexpr (x != 0) pxx += f[q];
-    if constexpr (y != 0) pyy += f[q];
-    if constexpr (z != 0) pzz += f[q];
-    if constexpr (x * y == 1) pxy += f[q];
-    if constexpr (x * y == -1) pxy -= f[q];
-    if constexpr (x * z == 1) pxz += f[q];
-    if constexpr (x * z == -1) pxz -= f[q];
-    if constexpr (y * z == 1) pyz += f[q];
-    if constexpr (y * z == -1) pyz -= f[q];
-  });
+  Real mom[10];
+  pair_moments<Real>([](int) constexpr { return true; }, [&](auto q) { return f[q]; }, mom);
+  const Real drho = mom[0], jx = mom[1], jy = mom[2], jz = mom[3];
+  const Real pxx = mom[4], pyy = mom[5], pzz = mom[6], pxy = mom[7], pxz = mom[8], pyz = mom[9];
   const Real rho0 = Real(p.rho0), ir = Real(p.inv_rho0);
   const Real a = Real(p.a_bp);
   const Real d3 = drho * Real(1.0 / 3.0);
@@ -632,43 +670,12 @@ __device__ __forceinline__ void load_group(const Real *__restrict__ ft, int64_t 
   static_for<Group<G>::N>([&](auto i) { f[i] = base[(int64_t)Group<G>::pop(i) * stride + col]; });
 }
 
-// Partial moment sums over the group's populations: drho, jx, jy, jz,
-// Pi_xx, Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz (compensated in FP32 for drho
-// and j, as cell_moments()).
+// Partial moment sums over the group's populations (both groups' sets are
+// closed under q -> -q): drho, jx, jy, jz, Pi_xx, Pi_yy, Pi_zz, Pi_xy,
+// Pi_xz, Pi_yz, formed as in pair_moments().
 template <typename Real, int G>
 __device__ __forceinline__ void partial_moments(const Real (&f)[Group<G>::N], Real (&m)[10]) {
-  CompSum<Real> r, ax, ay, az;
-  Real pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-  static_for<Group<G>::N>([&](auto i) {
-    constexpr int q = Group<G>::pop(i);
-    constexpr int x = kCx[q], y = kCy[q], z = kCz[q];
-    const Real v = f[i];
-    if constexpr (std::is_same<Real, double>::value) {
-      r.s += v;
-      if constexpr (x != 0) ax.s += Real(x) * v;
-      if constexpr (y != 0) ay.s += Real(y) * v;
-      if constexpr (z != 0) az.s += Real(z) * v;
-    } else {
-      r.add(v);
-      if constexpr (x == 1) ax.add(v);
-      if constexpr (x == -1) ax.sub(v);
-      if constexpr (y == 1) ay.add(v);
-      if constexpr (y == -1) ay.sub(v);
-      if constexpr (z == 1) az.add(v);
-      if constexpr (z == -1) az.sub(v);
-    }
-    if constexpr (x != 0) pxx += v;
-    if constexpr (y != 0) pyy += v;
-    if constexpr (z != 0) pzz += v;
-    if constexpr (x * y == 1) pxy += v;
-    if constexpr (x * y == -1) pxy -= v;
-    if constexpr (x * z == 1) pxz += v;
-    if constexpr (x * z == -1) pxz -= v;
-    if constexpr (y * z == 1) pyz += v;
-    if constexpr (y * z == -1) pyz -= v;
-  });
-  m[0] = r.value(); m[1] = ax.value(); m[2] = ay.value(); m[3] = az.value();
-  m[4] = pxx; m[5] = pyy; m[6] = pzz; m[7] = pxy; m[8] = pxz; m[9] = pyz;
+  pair_moments<Real>([](int q) constexpr { return group_of(q) == G; }, [&](auto q) { return f[local_of(q)]; }, m);
 }
 
 // The rest of publishing a cell, from its full moment sums m: B and f~+ of
