@@ -80,7 +80,9 @@ typedef struct dhit_params {
     int32_t tile_width; /* fused DUGKS kernel: width of a block's column tile, 16 or 32
                            (0 = the default, 32) */
     int32_t z_chunk;    /* fused DUGKS kernel: planes one block marches through,
-                           0 = default (32 for n >= 128, 16 for n >= 32, else n) */
+                           0 = chosen at create_box for the current device: the
+                           chunk ceil(n/k) >= min(n, 8) that minimises
+                           ceil(blocks / resident blocks) * (chunk + 2) */
     double nu;          /* kinematic viscosity, > 0 */
     double rho0;        /* mean density, > 0 (paper: 1) */
     double dt;          /* time step: LBE requires 1; DUGKS requires 0 < dt*sqrt(2) <= 1

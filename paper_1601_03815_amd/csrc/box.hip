@@ -198,6 +198,7 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
     dhit_box *b = new dhit_box();
     try {
       b->p = *pp;
+      if (b->p.method == DHIT_DUGKS && b->p.z_chunk == 0) b->p.z_chunk = dhit::fused_auto_chunk(b->p);
       b->n = pp->n;
       b->ncell = (int64_t)pp->n * pp->n * pp->n;
       b->elem = pp->precision == DHIT_FP32 ? 4 : 8;
@@ -218,7 +219,7 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
         if (hipMalloc(&b->f[0], pop) != hipSuccess || hipMalloc(&b->f[1], pop) != hipSuccess)
           fail(DHIT_ENOMEM, "cannot allocate population buffers");
       }
-      b->max_blocks = (int)reduction_blocks(*pp);
+      b->max_blocks = (int)reduction_blocks(b->p);
       if (hipMalloc(&b->partials, (size_t)b->max_blocks * 5 * sizeof(double)) != hipSuccess ||
           hipMalloc(&b->hist, (size_t)dhit::kHistoryCap * 5 * sizeof(double)) != hipSuccess)
         fail(DHIT_ENOMEM, "cannot allocate reduction buffers");

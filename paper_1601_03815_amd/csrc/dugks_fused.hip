@@ -1022,7 +1022,8 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
 // FP64 (split march, 512 threads): 132 KB of LDS, one block per compute
-// unit; FP32 (256 threads): 40 KB, four blocks per compute unit.
+// unit; FP32 (256 threads): 40 KB of LDS, two blocks per compute unit (its
+// registers allow two waves per SIMD).
 constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
@@ -1036,15 +1037,21 @@ int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_
   return tx * ty * ((n + chunk - 1) / chunk);
 }
 
+// Shortest z-chunk the balanced choice below takes (shorter chunks re-read
+// the two halo planes too often).
+constexpr int kMinAutoChunk = 8;
+
 // Tiles of a single-box fused launch with the box's tile width and z-chunk
-// (one block per tile; the grid is rounded up to a multiple of 8).
+// (one block per tile; the grid is rounded up to a multiple of 8).  With
+// z_chunk = 0 (not yet resolved) the count is that of the shortest chunk
+// the balanced choice can take, an upper bound for sizing buffers.
 int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
   const int n = p.n;
   const int w = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
   const int ix = w - 2, iy = 8 - 2;
   const int tx = (n + ix - 1) / ix;
   const int ty = (n + iy - 1) / iy;
-  const int cz = p.z_chunk ? p.z_chunk : fused_default_chunk(n);
+  const int cz = p.z_chunk ? p.z_chunk : std::min(n, kMinAutoChunk);
   const int nzc = (n + cz - 1) / cz;
   if (width) *width = w;
   if (tiles_x) *tiles_x = tx;
@@ -1086,6 +1093,59 @@ static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out
 }
 
 int fused_tile_width_of(int precision) { return fused_tile_width(precision); }
+
+// Blocks of the fused kernel of this precision and tile width that one
+// compute unit holds at once (registers and LDS decide: one for the FP64
+// split march, two for FP32 at width 32).
+static int fused_resident_blocks(int precision, int w) {
+  int nb = 0;
+  hipError_t e;
+  if (precision == DHIT_FP64)
+    e = w == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 16>), 2 * fused::Tile<16>::NT, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 32>), 2 * fused::Tile<32>::NT, 0);
+  else
+    e = w == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 16>), fused::Tile<16>::NT, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 32>), fused::Tile<32>::NT, 0);
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+// z-chunk that balances a launch.  Its blocks run in rounds of `slots`
+// (compute units x resident blocks); a block marching c planes costs about
+// c + 2 plane iterations (the two halo planes), so the launch costs about
+// ceil(blocks / slots) (c + 2).  Among the chunks ceil(n / k) of at least
+// kMinAutoChunk planes (or n, if smaller) the cheapest is taken, the
+// longest of equal ones.  At 256^3 this picks 37 planes in FP64 (1 block
+// per unit, 387 column tiles: 11 rounds of 39 against 13 of 34 for 32).
+int fused_balanced_chunk(int n, int tiles_xy, int slots) {
+  const int cmin = std::min(n, kMinAutoChunk);
+  int best = n;
+  int64_t best_cost = INT64_MAX;
+  for (int k = 1; (n + k - 1) / k >= cmin; ++k) {
+    const int c = (n + k - 1) / k;
+    if (k > 1 && c == (n + k - 2) / (k - 1)) continue;  // same chunk as k - 1
+    const int64_t blocks = (int64_t)tiles_xy * ((n + c - 1) / c);
+    const int64_t cost = (blocks + slots - 1) / slots * (c + 2);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
+}
+
+// Default z-chunk of a box on the current device.
+int fused_auto_chunk(const dhit_params &p) {
+  int w, tx, ty;
+  fused_dugks_blocks(p, &w, &tx, &ty, nullptr);
+  int dev = 0, cus = 0;
+  DHIT_HIP(hipGetDevice(&dev));
+  DHIT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return fused_balanced_chunk(p.n, tx * ty, std::max(cus, 1) * fused_resident_blocks(p.precision, w));
+}
 
 void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid) {
   grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8

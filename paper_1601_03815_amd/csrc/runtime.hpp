@@ -135,6 +135,8 @@ void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbo
 void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commit);
 int fused_tile_width_of(int precision);
 int fused_default_chunk(int n);
+int fused_balanced_chunk(int n, int tiles_xy, int slots);
+int fused_auto_chunk(const dhit_params &p);
 int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_y);
 
 // Spectrum (spectrum.hip)
