@@ -517,7 +517,10 @@ __device__ __forceinline__ void fused_tile(const Real *__restrict__ ft, Real *__
         xy_face(I1{}, I0{}, I0{}, I1{});     // y+
         xy_face(I1{}, I0{}, Im1{}, Im1{});   // y-
         const int cell = (p_ - 1) * n * n + col;
-        static_for<kQ>([&](auto q) { __builtin_nontemporal_store(acc_c[q], &out[(int64_t)q * stride + cell]); });
+        // plain (L2-allocating) stores: a tile row's 30 updated cells do not
+        // fill whole 128-byte lines, and L2 merges them with the neighbouring
+        // tiles' rows before they are written back
+        static_for<kQ>([&](auto q) { out[(int64_t)q * stride + cell] = acc_c[q]; });
         sums_of_populations<Real>(acc_c, p.inv_rho0, v);
       }
     }
@@ -941,7 +944,7 @@ __device__ __forceinline__ void split_tile(const Real *__restrict__ ft, Real *__
           double r = 0, ax = 0, ay = 0, az = 0;
           static_for<NG>([&](auto i) {
             constexpr int q = Group<G>::pop(i);
-            __builtin_nontemporal_store(acc_c[i], &out[(int64_t)q * stride + cell]);
+            out[(int64_t)q * stride + cell] = acc_c[i];  // plain stores, as in fused_tile
             const double x = (double)acc_c[i];
             r += x;
             if constexpr (kCx[q] != 0) ax += kCx[q] * x;
