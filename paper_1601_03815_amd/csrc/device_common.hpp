@@ -139,6 +139,18 @@ __device__ __forceinline__ void sums_of_cell(Real drho, Real jx, Real jy, Real j
   v[4] += 0.5 * (x * x + y * y + z * z) * inv_rho0 * inv_rho0;
 }
 
+// Pointer into global memory.  The device functions that stream population
+// fields take these, so that their accesses compile to global instructions
+// also where a kernel reads the field pointers from a device table (through
+// a generic pointer they would compile to flat instructions, which count
+// against the LDS counter as well: every LDS wait would also wait for memory).
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T> *to_global(T *p) {
+  return (global_t<T> *)p;
+}
+
 // Writes the block's five sums to partials laid out [5][nblocks], using
 // smem (at least one row of five doubles per wavefront of the block) for
 // the reduction.
@@ -146,7 +158,7 @@ __device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], doub
                                                      double (*smem)[kNumSums]) {
   block_sum5(v, smem);
   if (threadIdx.x == 0) {
-    static_for<kNumSums>([&](auto i) { partials[(int64_t)i * nblocks + block] = v[i]; });
+    static_for<kNumSums>([&](auto i) { to_global(partials)[(int64_t)i * nblocks + block] = v[i]; });
   }
 }
 __device__ __forceinline__ void write_block_partials(double (&v)[kNumSums], double *partials, int nblocks,

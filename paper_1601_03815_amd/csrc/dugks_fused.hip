@@ -289,10 +289,10 @@ __device__ __forceinline__ void sub_face(const Real (&m)[4], const StepParams &p
 // Issues the loads of the 19 f~ of the column's cell in plane `plane`
 // (periodic in z).
 template <typename Real>
-__device__ __forceinline__ void load_raw(const Real *__restrict__ ft, int64_t stride, int n, int col, int plane,
+__device__ __forceinline__ void load_raw(const global_t<Real> *__restrict__ ft, int64_t stride, int n, int col, int plane,
                                          Real (&f)[kQ]) {
   const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
-  const Real *base = ft + (int64_t)z * n * n;
+  const global_t<Real> *base = ft + (int64_t)z * n * n;
   static_for<kQ>([&](auto q) { f[q] = base[(int64_t)q * stride + col]; });
 }
 
@@ -398,7 +398,7 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real 
 // moments of the updated cells to v.  L is the block's LDS, kLdsValues
 // values per column: P [kNPop][NT], Q [2][kNQ][NT], Z [3][kNZ][NT].
 template <typename Real, int W>
-__device__ __forceinline__ void fused_tile(const Real *__restrict__ ft, Real *__restrict__ out, const StepParams &p,
+__device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
                                            int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   const int n = p.n;
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_
   const int by = (t / tiles_x) % tiles_y;
   const int bz = t / (tiles_x * tiles_y);
   double v[kNumSums] = {0, 0, 0, 0, 0};
-  fused_tile<Real, W>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+  fused_tile<Real, W>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
   // the march ends with a barrier: L is free for the block reduction
   write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
 }
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_
     const int by = (local / d.tiles_x) % d.tiles_y;
     const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
-    fused_tile<Real, W>(static_cast<const Real *>(d.f[d.cur]), static_cast<Real *>(d.f[d.cur ^ 1]), d.sp, bx, by, bz,
+    fused_tile<Real, W>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp, bx, by, bz,
                         d.nz_chunk, L, v);
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
@@ -666,10 +666,10 @@ constexpr int kSplitValues = kSA + 4;
 
 // Loads of the group's populations of the column's cell in plane `plane`.
 template <typename Real, int G>
-__device__ __forceinline__ void load_group(const Real *__restrict__ ft, int64_t stride, int n, int col, int plane,
+__device__ __forceinline__ void load_group(const global_t<Real> *__restrict__ ft, int64_t stride, int n, int col, int plane,
                                            Real (&f)[Group<G>::N]) {
   const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
-  const Real *base = ft + (int64_t)z * n * n;
+  const global_t<Real> *base = ft + (int64_t)z * n * n;
   static_for<Group<G>::N>([&](auto i) { f[i] = base[(int64_t)Group<G>::pop(i) * stride + col]; });
 }
 
@@ -730,7 +730,7 @@ __device__ __forceinline__ void publish_group(const Real (&f)[Group<G>::N], cons
 // The z-march of group G of a tile (see above).  L: the block's LDS,
 // kSplitValues values per column.
 template <typename Real, int W, int G>
-__device__ __forceinline__ void split_tile(const Real *__restrict__ ft, Real *__restrict__ out, const StepParams &p,
+__device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
                                            int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   constexpr int NG = Group<G>::N;
@@ -989,9 +989,9 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const Real
   const int bz = t / (tiles_x * tiles_y);
   double v[kNumSums] = {0, 0, 0, 0, 0};
   if (threadIdx.x < Tile<W>::NT)
-    split_tile<Real, W, 0>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+    split_tile<Real, W, 0>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
   else
-    split_tile<Real, W, 1>(ft, out, p, bx, by, bz, nz_chunk, L, v);
+    split_tile<Real, W, 1>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
   write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
 }
 
@@ -1010,8 +1010,8 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
     const int by = (local / d.tiles_x) % d.tiles_y;
     const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
-    const Real *src = static_cast<const Real *>(d.f[d.cur]);
-    Real *dst = static_cast<Real *>(d.f[d.cur ^ 1]);
+    const global_t<Real> *src = to_global(static_cast<const Real *>(d.f[d.cur]));
+    global_t<Real> *dst = to_global(static_cast<Real *>(d.f[d.cur ^ 1]));
     if (threadIdx.x < Tile<W>::NT)
       split_tile<Real, W, 0>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
     else

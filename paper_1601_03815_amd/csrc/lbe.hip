@@ -17,7 +17,7 @@ namespace dhit {
 
 // Update of one cell; adds its moments to the block's sums v.
 template <int C, typename Real>
-__device__ __forceinline__ void lbe_cell(const Real *__restrict__ src, Real *__restrict__ dst, const StepParams &p,
+__device__ __forceinline__ void lbe_cell(const global_t<Real> *__restrict__ src, global_t<Real> *__restrict__ dst, const StepParams &p,
                                          int cell, double (&v)[kNumSums]) {
   const int n = p.n;
   const int64_t stride = p.stride;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void lbe_pull_kernel(const Real *__restrict
                                                           StepParams p, int ncell, double *__restrict__ partials) {
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   double v[kNumSums] = {0, 0, 0, 0, 0};
-  if (cell < ncell) lbe_cell<C, Real>(src, dst, p, cell, v);
+  if (cell < ncell) lbe_cell<C, Real>(to_global(src), to_global(dst), p, cell, v);
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
 }
 
@@ -67,7 +67,8 @@ __global__ __launch_bounds__(kBlock) void lbe_batch_kernel(BatchBox *__restrict_
     const int cell = local * kBlock + threadIdx.x;
     double v[kNumSums] = {0, 0, 0, 0, 0};
     if (cell < d.ncell)
-      lbe_cell<C, Real>(static_cast<const Real *>(d.f[d.cur]), static_cast<Real *>(d.f[d.cur ^ 1]), d.sp, cell, v);
+      lbe_cell<C, Real>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp,
+                        cell, v);
     write_block_partials(v, d.partials, d.items, local);
     __syncthreads();
   }
