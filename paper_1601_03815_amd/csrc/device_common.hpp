@@ -63,24 +63,52 @@ __device__ __forceinline__ void cell_moments(const Real (&f)[kQ], Real &drho, Re
 }
 
 // Discrete incompressible equilibrium of Sec. II.A with RT = 1/3:
-// f_q^eq = W_q [drho + rho0 (3 xi.u + 9/2 (xi.u)^2 - 3/2 |u|^2)], u = j/rho0.
+// f_q^eq = W_q [drho + rho0 (3 xi.u + 9/2 (xi.u)^2 - 3/2 |u|^2)], u = j/rho0,
+// evaluated as W_q (base + 9/2 rho0 (xi.u)^2) + L_q rho0 xi.u with
+// base = drho - 3/2 rho0 |u|^2 and L_q = 3 W_q (1/6 on the axes, 1/12 on the
+// diagonals).  The momentum of the linear term is u sum_q L_q xi_qx^2 =
+// u (2 L_axis + 8 L_diag); with 3 W_q rounded to the working precision that
+// factor is 1 + d (d = 7e-9 in FP32), and a BGK or DUGKS collision then adds
+// a fixed fraction of d j to the momentum at every step (a steady energy
+// drift, 3e-8 per DUGKS step in FP32).  L_diag is rounded and L_axis taken as
+// (1 - 8 L_diag)/2, which is exact, so that the factor is exactly 1.
+template <typename Real>
+constexpr Real kLinDiag = Real(1.0 / 12.0);
+template <typename Real>
+constexpr Real kLinAxis = (Real(1) - Real(8) * kLinDiag<Real>) / Real(2);
+
+// xi_q . u
+template <int Q, typename Real>
+__device__ __forceinline__ Real xi_dot(Real ux, Real uy, Real uz) {
+  Real xu = Real(0);
+  if constexpr (kCx[Q] == 1) xu += ux;
+  if constexpr (kCx[Q] == -1) xu -= ux;
+  if constexpr (kCy[Q] == 1) xu += uy;
+  if constexpr (kCy[Q] == -1) xu -= uy;
+  if constexpr (kCz[Q] == 1) xu += uz;
+  if constexpr (kCz[Q] == -1) xu -= uz;
+  return xu;
+}
+
+// f_Q^eq from base and xu = xi_Q . u (see above).
+template <int Q, typename Real>
+__device__ __forceinline__ Real equilibrium_q(Real base, Real xu, Real rho0) {
+  constexpr Real w = Real(kWeight(Q));
+  constexpr Real l = speed2(Q) == 0 ? Real(0) : (speed2(Q) == 1 ? kLinAxis<Real> : kLinDiag<Real>);
+  const Real even = w * (base + Real(4.5) * rho0 * xu * xu);
+  if constexpr (Q == 0)
+    return even;
+  else
+    return even + l * rho0 * xu;
+}
+
 template <typename Real>
 __device__ __forceinline__ void equilibrium(Real drho, Real jx, Real jy, Real jz, Real rho0, Real inv_rho0,
                                             Real (&feq)[kQ]) {
   const Real ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
   const Real uu = ux * ux + uy * uy + uz * uz;
   const Real base = drho - Real(1.5) * rho0 * uu;
-  static_for<kQ>([&](auto q) {
-    constexpr Real w = Real(kWeight(q));
-    Real xu = Real(0);
-    if constexpr (kCx[q] == 1) xu += ux;
-    if constexpr (kCx[q] == -1) xu -= ux;
-    if constexpr (kCy[q] == 1) xu += uy;
-    if constexpr (kCy[q] == -1) xu -= uy;
-    if constexpr (kCz[q] == 1) xu += uz;
-    if constexpr (kCz[q] == -1) xu -= uz;
-    feq[q] = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
-  });
+  static_for<kQ>([&](auto q) { feq[q] = equilibrium_q<q, Real>(base, xi_dot<q>(ux, uy, uz), rho0); });
 }
 
 // Sum of five doubles over the block; thread 0 gets the block total.

@@ -375,19 +375,11 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real 
   // f~+ = 4/3 B - 1/3 f~ as B + (B - f~)/3, so that an equilibrium cell maps
   // to itself exactly in any precision (rounded 4/3 and 1/3, or a and b,
   // would otherwise scale the state by 1 + O(ulp) every step).  f^eq is the
-  // equilibrium of Sec. II.A, as in equilibrium().
+  // equilibrium of Sec. II.A, evaluated as in equilibrium().
   const Real ux = jx * ir, uy = jy * ir, uz = jz * ir;
   const Real base = drho - Real(1.5) * rho0 * (ux * ux + uy * uy + uz * uz);
   static_for<kQ>([&](auto q) {
-    constexpr Real w = Real(kWeight(q));
-    Real xu = Real(0);
-    if constexpr (kCx[q] == 1) xu += ux;
-    if constexpr (kCx[q] == -1) xu -= ux;
-    if constexpr (kCy[q] == 1) xu += uy;
-    if constexpr (kCy[q] == -1) xu -= uy;
-    if constexpr (kCz[q] == 1) xu += uz;
-    if constexpr (kCz[q] == -1) xu -= uz;
-    const Real feq = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
+    const Real feq = equilibrium_q<q, Real>(base, xi_dot<q>(ux, uy, uz), rho0);
     const Real b = feq + a * (f[q] - feq);
     if constexpr (pop_index(q) >= 0) P[pop_index(q) * NT] = b;
     use(q, b, b + (b - f[q]) * Real(1.0 / 3.0));
@@ -712,15 +704,7 @@ __device__ __forceinline__ void publish_group(const Real (&f)[Group<G>::N], cons
   const Real base = drho - Real(1.5) * rho0 * (ux * ux + uy * uy + uz * uz);
   static_for<Group<G>::N>([&](auto i) {
     constexpr int q = Group<G>::pop(i);
-    constexpr Real w = Real(kWeight(q));
-    Real xu = Real(0);
-    if constexpr (kCx[q] == 1) xu += ux;
-    if constexpr (kCx[q] == -1) xu -= ux;
-    if constexpr (kCy[q] == 1) xu += uy;
-    if constexpr (kCy[q] == -1) xu -= uy;
-    if constexpr (kCz[q] == 1) xu += uz;
-    if constexpr (kCz[q] == -1) xu -= uz;
-    const Real feq = w * (base + rho0 * (Real(3) * xu + Real(4.5) * xu * xu));
+    const Real feq = equilibrium_q<q, Real>(base, xi_dot<q>(ux, uy, uz), rho0);
     const Real b = feq + a * (f[i] - feq);
     if constexpr (pop_index(q) >= 0) P[pop_index(q) * NT] = b;
     use(std::integral_constant<int, q>{}, b, b + (b - f[i]) * Real(1.0 / 3.0));

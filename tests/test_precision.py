@@ -24,6 +24,17 @@ def test_fp32_spectrum_error_below_1e4_over_horizon(method):
     assert max(r["eps_rel"] for r in out) < 1e-4
 
 
+def test_fp32_dugks_energy_has_no_systematic_drift():
+    """DHIT 32^3, nu = 0.01, 800 DUGKS steps: the FP32 kinetic energy stays
+    within 4e-6 of the FP64 one.  An equilibrium whose linear coefficients
+    carry the weights' FP32 rounding (momentum j (1 + 7e-9)) makes every DUGKS
+    collision add a fixed fraction of it: K then drifts by ~3e-8 per step,
+    2.6e-5 after 800 steps."""
+    u = synth.dhit_field(32, seed=3, k0=4, u_rms=0.05)
+    out, _ = compare_fp32_fp64(u, "dugks", 0.01, 800, 200, threshold=1e-4)
+    assert max(r["K_rel"] for r in out) < 4e-6, out
+
+
 @pytest.mark.parametrize("method", ["mrt", "dugks"])
 def test_fp64_spectrum_matches_oracle_over_horizon(method):
     """DHIT 24^3: the FP64 GPU spectrum, K and eps match the oracle's at every
