@@ -15,9 +15,9 @@ constexpr int kNumSums = 5;            // sum drho, sum jx, sum jy, sum jz, 1/2 
 
 // Compensated summation (Kahan): s carries the running sum and c the
 // rounding error of the last addition (with its sign reversed), which is
-// fed back into the next term, so that the error of a sum of m terms stays
-// O(eps) instead of O(m eps).  Used for the per-cell moment sums of FP32
-// boxes.
+// fed back into the next term, so that the error of a sum of m terms is
+// about 2 eps sum |x_i| instead of (m - 1) eps sum |x_i|.  Used for the
+// per-cell moment sums of FP32 boxes.
 template <typename Real>
 struct CompSum {
   Real s = Real(0), c = Real(0);

@@ -41,8 +41,8 @@
 // Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column.
 //
 // Two marches implement this.  fused_tile (FP32): one thread per column,
-// 40 values of LDS per column (40 KB for a 32 x 8 tile, four blocks per
-// compute unit).  split_tile (FP64): two threads per column, one in each of
+// 40 values of LDS per column (40 KB for a 32 x 8 tile; its registers allow
+// two blocks per compute unit).  split_tile (FP64): two threads per column, one in each of
 // two groups that hold about half of the populations each (see below), so
 // that a thread's registers fit two waves per SIMD; 66 values per column.
 // LDS reads are gathered (see gathered()) so that each chunk of work waits
