@@ -114,6 +114,18 @@ struct Unit {
   static constexpr int x = T == 0, y = T == 1, z = T == 2;
 };
 
+// Value of the previous lane of the wavefront (lane 0 gets 0): a DPP
+// whole-wavefront shift right by one lane, one move per 32 bits.
+__device__ __forceinline__ int from_previous_lane(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_previous_lane(float v) {
+  return __builtin_bit_cast(float, from_previous_lane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double from_previous_lane(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = from_previous_lane((int)b), hi = from_previous_lane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Reads of one plane: populations from P, in-plane moment fields from Q,
 // z-differentiated fields from Z (each offset to the thread's column; a
 // plane whose populations or Q fields are no longer held has null there).
@@ -404,6 +416,7 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   gy = gy < 0 ? gy + n : (gy >= n ? gy % n : gy);
   const int col = gy * n + gx;
   const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
+  const bool xface = tx <= TX - 2 && ty >= 1 && ty <= TY - 2;  // forms the x+ face (see below)
   const Real h = Real(p.h), dt = Real(p.dt);
   const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
   Real *const LP = L + tid;
@@ -480,34 +493,43 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
           }
         });
       });
-      if (has_prev) {
-        // x- and y-faces of centre p-1: in-plane part from plane p-1, the
-        // z-tangential gradients -h/4 [(M_L + M_R)(p) - (M_L + M_R)(p-2)]
-        const Real hq = Real(0.25) * h;
-        auto xy_face = [&](auto D, auto LX, auto LY, auto S) {
-          Real m[4];
-          gathered<Real, W>(c1, c1, [&](const auto &g, const auto &) {
-            Real t[4];
-            face_inplane<D, LX, LY>(g, h, t);
-            if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { m[i] = t[i]; });
-          });
-          gathered<Real, W>(c, c2, [&](const auto &g, const auto &g2) {
-            Real s1[4], s0[4];
-            face_zsum<D, LX, LY>(g, s1);
-            face_zsum<D, LX, LY>(g2, s0);
-            if constexpr (std::decay_t<decltype(g)>::use) {
-              static_for<4>([&](auto i) { m[i] -= hq * (s1[i] - s0[i]); });
-              sub_face<D, S, Real>(m, p, dtbe, acc_c);
-            }
-          });
-        };
-        using I0 = std::integral_constant<int, 0>;
-        using I1 = std::integral_constant<int, 1>;
-        using Im1 = std::integral_constant<int, -1>;
-        xy_face(I0{}, I0{}, I0{}, I1{});     // x+
-        xy_face(I0{}, Im1{}, I0{}, Im1{});   // x-
-        xy_face(I1{}, I0{}, I0{}, I1{});     // y+
-        xy_face(I1{}, I0{}, Im1{}, Im1{});   // y-
+    }
+    if (has_prev) {
+      // x- and y-faces of centre p-1: in-plane part from plane p-1, the
+      // z-tangential gradients -h/4 [(M_L + M_R)(p) - (M_L + M_R)(p-2)]
+      const Real hq = Real(0.25) * h;
+      auto face_moments = [&](auto D, auto LX, auto LY, Real (&m)[4]) {
+        gathered<Real, W>(c1, c1, [&](const auto &g, const auto &) {
+          Real t[4];
+          face_inplane<D, LX, LY>(g, h, t);
+          if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { m[i] = t[i]; });
+        });
+        gathered<Real, W>(c, c2, [&](const auto &g, const auto &g2) {
+          Real s1[4], s0[4];
+          face_zsum<D, LX, LY>(g, s1);
+          face_zsum<D, LX, LY>(g2, s0);
+          if constexpr (std::decay_t<decltype(g)>::use) static_for<4>([&](auto i) { m[i] -= hq * (s1[i] - s0[i]); });
+        });
+      };
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using Im1 = std::integral_constant<int, -1>;
+      // Each x-face is formed once: every column of an interior row but the
+      // last (the halo column 0 too) forms its x+ face, and a column's x-
+      // face is the x+ face of the column before it, the previous lane (a
+      // tile row is 32 consecutive lanes of one wavefront).  The lane shift
+      // runs with every lane active.
+      Real mxp[4] = {Real(0), Real(0), Real(0), Real(0)}, mxm[4];
+      if (xface) face_moments(I0{}, I0{}, I0{}, mxp);
+      static_for<4>([&](auto i) { mxm[i] = from_previous_lane(mxp[i]); });
+      if (inner) {
+        sub_face<0, 1, Real>(mxp, p, dtbe, acc_c);    // x+
+        sub_face<0, -1, Real>(mxm, p, dtbe, acc_c);   // x-
+        Real my[4];
+        face_moments(I1{}, I0{}, I0{}, my);
+        sub_face<1, 1, Real>(my, p, dtbe, acc_c);     // y+
+        face_moments(I1{}, I0{}, Im1{}, my);
+        sub_face<1, -1, Real>(my, p, dtbe, acc_c);    // y-
         const int cell = (p_ - 1) * n * n + col;
         // plain (L2-allocating) stores: a tile row's 30 updated cells do not
         // fill whole 128-byte lines, and L2 merges them with the neighbouring
