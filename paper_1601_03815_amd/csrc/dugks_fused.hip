@@ -751,6 +751,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   gy = gy < 0 ? gy + n : (gy >= n ? gy % n : gy);
   const int col = gy * n + gx;
   const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
+  const bool xface = tx <= TX - 2 && ty >= 1 && ty <= TY - 2;  // A: forms an x+ face
   const Real h = Real(p.h), dt = Real(p.dt);
   const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
   const double ir = p.inv_rho0;
@@ -879,7 +880,9 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           });
         }
       }
-      if (has_prev) {
+    }
+    if (has_prev) {
+      {
         // the group's two faces of centre p-1: in-plane part from plane
         // p-1, z-tangential gradients -h/4 [(M_L + M_R)(p) - (M_L + M_R)(p-2)];
         // written for the other group (A's into RB, B's into RA)
@@ -900,10 +903,21 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
         };
         using I0 = std::integral_constant<int, 0>;
         using Im1 = std::integral_constant<int, -1>;
-        face(I0{}, I0{}, fx[0]);                        // upper face
-        if constexpr (G == 0) face(Im1{}, I0{}, fx[1]);  // x-
-        else face(I0{}, Im1{}, fx[1]);                   // y-
-        static_for<2>([&](auto f) { static_for<4>([&](auto i) { (G == 0 ? RB : RA)[(f * 4 + i) * NT] = fx[f][i]; }); });
+        if constexpr (G == 0) {
+          // each x-face formed once, as in fused_tile: x+ by every column of
+          // an interior row but the last, x- from the previous lane
+          Real xp[4] = {Real(0), Real(0), Real(0), Real(0)};
+          if (xface) face(I0{}, I0{}, xp);
+          static_for<4>([&](auto i) {
+            fx[0][i] = xp[i];
+            fx[1][i] = from_previous_lane(xp[i]);
+          });
+        } else if (inner) {
+          face(I0{}, I0{}, fx[0]);   // y+
+          face(I0{}, Im1{}, fx[1]);  // y-
+        }
+        if (inner)
+          static_for<2>([&](auto f) { static_for<4>([&](auto i) { (G == 0 ? RB : RA)[(f * 4 + i) * NT] = fx[f][i]; }); });
       }
     }
     phase();
