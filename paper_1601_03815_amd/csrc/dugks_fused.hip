@@ -668,8 +668,10 @@ constexpr int local_of(int q) {
 }
 // LDS per column after the plane buffers:
 //   RA [12]: A's partial moments (read by B after the first barrier of an
-//            iteration), then the y-face moments [0..8) and the z-face
-//            moments [8..12) formed by B (read by A after the third);
+//            iteration), then the moments [0..4) of the y-face between the
+//            column and the next row and the z-face moments [8..12), formed
+//            by B (read by both groups after the third; a column's lower
+//            y-face is the upper one of the column W before it);
 //   RB [10]: B's partial moments, then the x-face moments [0..8) formed by A;
 //   SA [4]:  A's part of the sums of its last stored cell (read by B in the
 //            next iteration).
@@ -752,6 +754,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   const int col = gy * n + gx;
   const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
   const bool xface = tx <= TX - 2 && ty >= 1 && ty <= TY - 2;  // A: forms an x+ face
+  const bool yface = tx >= 1 && tx <= TX - 2 && ty <= TY - 2;  // B: forms a y+ face
   const Real h = Real(p.h), dt = Real(p.dt);
   const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
   const double ir = p.inv_rho0;
@@ -912,12 +915,17 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
             fx[0][i] = xp[i];
             fx[1][i] = from_previous_lane(xp[i]);
           });
-        } else if (inner) {
-          face(I0{}, I0{}, fx[0]);   // y+
-          face(I0{}, Im1{}, fx[1]);  // y-
+        } else {
+          // y+ faces only, by every interior column of every row but the
+          // last (halo row 0 too); the y- face is read back from the row below
+          if (yface) {
+            face(I0{}, I0{}, fx[0]);
+            static_for<4>([&](auto i) { RA[i * NT] = fx[0][i]; });
+          }
         }
-        if (inner)
-          static_for<2>([&](auto f) { static_for<4>([&](auto i) { (G == 0 ? RB : RA)[(f * 4 + i) * NT] = fx[f][i]; }); });
+        if constexpr (G == 0) {
+          if (inner) static_for<2>([&](auto f) { static_for<4>([&](auto i) { RB[(f * 4 + i) * NT] = fx[f][i]; }); });
+        }
       }
     }
     phase();
@@ -950,7 +958,12 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           // equilibrium parts of the four x/y-faces of centre p-1 for this
           // group's populations: its own two faces and the other group's
           Real fo[2][4];
-          static_for<2>([&](auto f) { static_for<4>([&](auto i) { fo[f][i] = (G == 0 ? RA : RB)[(f * 4 + i) * NT]; }); });
+          if constexpr (G == 0) {
+            static_for<4>([&](auto i) { fo[0][i] = RA[i * NT]; fo[1][i] = RA[i * NT - W]; });
+          } else {
+            static_for<2>([&](auto f) { static_for<4>([&](auto i) { fo[f][i] = RB[(f * 4 + i) * NT]; }); });
+            static_for<4>([&](auto i) { fx[1][i] = RA[i * NT - W]; });
+          }
           using Ip = std::integral_constant<int, 1>;
           using Im = std::integral_constant<int, -1>;
           if constexpr (G == 0) {
