@@ -41,8 +41,8 @@
 // Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column.
 //
 // Two marches implement this.  fused_tile (FP32): one thread per column,
-// 40 values of LDS per column (40 KB for a 32 x 8 tile; its registers allow
-// two blocks per compute unit).  split_tile (FP64): two threads per column, one in each of
+// 44 values of LDS per column (44 KB for a 32 x 8 tile, three blocks per
+// compute unit).  split_tile (FP64): two threads per column, one in each of
 // two groups that hold about half of the populations each (see below), so
 // that a thread's registers fit two waves per SIMD; 66 values per column.
 // LDS reads are gathered (see gathered()) so that each chunk of work waits
@@ -74,6 +74,9 @@ enum : int { kR0 = 19, kJx, kJy, kJz, kPxx, kPxy, kPxz, kPyy, kPyz, kPzz };
 // across x/y-faces (three planes).
 constexpr int kNPop = 16, kNQ = 6, kNZ = 4;
 constexpr int kLdsValues = kNPop + 2 * kNQ + 3 * kNZ;  // per column
+// The one-thread march adds the moments of the y-face between each column
+// and the next row (read back by the column above as its lower y-face).
+constexpr int kFusedValues = kLdsValues + 4;
 constexpr int pop_index(int id) { return (id >= 1 && id <= 4) ? id - 1 : ((id >= 7 && id <= 18) ? id - 3 : -1); }
 constexpr int q_index(int id) {
   switch (id) {
@@ -399,7 +402,7 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real 
 }
 
 // The z-march of one tile (bx, by) over the z-chunk bz of a box; adds the
-// moments of the updated cells to v.  L is the block's LDS, kLdsValues
+// moments of the updated cells to v.  L is the block's LDS, kFusedValues
 // values per column: P [kNPop][NT], Q [2][kNQ][NT], Z [3][kNZ][NT].
 template <typename Real, int W>
 __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
@@ -417,11 +420,13 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   const int col = gy * n + gx;
   const bool inner = tx >= 1 && tx <= TX - 2 && ty >= 1 && ty <= TY - 2 && (x0 + tx - 1) < n && (y0 + ty - 1) < n;
   const bool xface = tx <= TX - 2 && ty >= 1 && ty <= TY - 2;  // forms the x+ face (see below)
+  const bool yface = tx >= 1 && tx <= TX - 2 && ty <= TY - 2;  // forms the y+ face
   const Real h = Real(p.h), dt = Real(p.dt);
   const Real dtal = dt * Real(p.alpha), dtbe = dt * Real(p.beta);
   Real *const LP = L + tid;
   Real *const LQ = L + kNPop * NT + tid;
   Real *const LZ = L + (kNPop + 2 * kNQ) * NT + tid;
+  Real *const LY = L + kLdsValues * NT + tid;
 
   Real pf[kQ];        // f~ of the plane being published (loaded one plane ahead)
   Real acc_c[kQ];     // result of centre p-1, completed in this iteration
@@ -432,9 +437,29 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   static_for<10>([&](auto i) { nxt[i] = Real(0); });
   static_for<4>([&](auto i) { zl[i] = Real(0); });
 
+  // Completes centre `plane` (acc_c): its lower y-face, read from the slot
+  // of the column W before, the store and the sums.  Runs after the barrier
+  // that ends the iteration which formed the faces.
+  auto finish = [&](int plane) {
+    Real ym[4];
+    static_for<4>([&](auto i) { ym[i] = LY[i * NT - W]; });
+    sub_face<1, -1, Real>(ym, p, dtbe, acc_c);
+    const int cell = plane * n * n + col;
+    // plain (L2-allocating) stores: a tile row's 30 updated cells do not
+    // fill whole 128-byte lines, and L2 merges them with the neighbouring
+    // tiles' rows before they are written back
+    static_for<kQ>([&](auto q) { out[(int64_t)q * stride + cell] = acc_c[q]; });
+    sums_of_populations<Real>(acc_c, p.inv_rho0, v);
+  };
+
   load_raw<Real>(ft, stride, n, col, z0 - 1, pf);
   int q2 = 0, q3 = 0;  // Q slot and Z slot of plane p
-  for (int p_ = z0 - 1; p_ <= z1; ++p_) {
+  // One iteration past the chunk's end only finishes its last centre, so
+  // that every centre is completed by the same code (and rounds the same
+  // whatever the chunk length).
+  for (int p_ = z0 - 1; p_ <= z1 + 1; ++p_) {
+    if (p_ - 1 > z0 && inner) finish(p_ - 2);  // the centre the last iteration formed
+    if (p_ > z1) break;
     const bool has_prev = p_ > z0;          // centre p-1 is in the chunk
     const bool has_cur = p_ >= z0 && p_ < z1;
     const int q2m = q2 ^ 1, q3m = q3 == 0 ? 2 : q3 - 1, q3mm = q3 == 2 ? 0 : q3 + 1;
@@ -522,20 +547,19 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
       Real mxp[4] = {Real(0), Real(0), Real(0), Real(0)}, mxm[4];
       if (xface) face_moments(I0{}, I0{}, I0{}, mxp);
       static_for<4>([&](auto i) { mxm[i] = from_previous_lane(mxp[i]); });
+      // The y-face between the column and the next row is formed once too,
+      // by every interior column of every row but the last (halo row 0
+      // too), and left in LY for the column above, which applies it as its
+      // lower face in finish() after the barrier that ends this iteration.
+      Real my[4];
+      if (yface) {
+        face_moments(I1{}, I0{}, I0{}, my);
+        static_for<4>([&](auto i) { LY[i * NT] = my[i]; });
+      }
       if (inner) {
         sub_face<0, 1, Real>(mxp, p, dtbe, acc_c);    // x+
         sub_face<0, -1, Real>(mxm, p, dtbe, acc_c);   // x-
-        Real my[4];
-        face_moments(I1{}, I0{}, I0{}, my);
         sub_face<1, 1, Real>(my, p, dtbe, acc_c);     // y+
-        face_moments(I1{}, I0{}, Im1{}, my);
-        sub_face<1, -1, Real>(my, p, dtbe, acc_c);    // y-
-        const int cell = (p_ - 1) * n * n + col;
-        // plain (L2-allocating) stores: a tile row's 30 updated cells do not
-        // fill whole 128-byte lines, and L2 merges them with the neighbouring
-        // tiles' rows before they are written back
-        static_for<kQ>([&](auto q) { out[(int64_t)q * stride + cell] = acc_c[q]; });
-        sums_of_populations<Real>(acc_c, p.inv_rho0, v);
       }
     }
     phase();
@@ -586,10 +610,12 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   }
 }
 
-// Register budget: FP32 tiles are held to 256 registers (two waves per
-// SIMD); the FP64 march needs more, and runs one wave per SIMD.
+// Register budget of the one-thread march: in FP32 it is held to 168
+// registers, three waves per SIMD (three blocks of 44 KB of LDS per compute
+// unit); the march is still issue-bound at two, and the third wave covers
+// the LDS and memory waits.  (FP64 tiles use the split march.)
 template <typename Real>
-constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
+constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 3 : 1;
 
 // Tile of a block, numbered so that the blocks one XCD runs (blocks are
 // dealt to the eight XCDs in turn) take consecutive tiles: block b of a
@@ -601,7 +627,7 @@ template <typename Real, int W>
 __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
                                                                   StepParams p, int tiles_x, int tiles_y,
                                                                   int nz_chunk, int ntiles, double *__restrict__ partials) {
-  __shared__ Real L[kLdsValues * Tile<W>::NT];
+  __shared__ Real L[kFusedValues * Tile<W>::NT];
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   const int bx = t % tiles_x;
@@ -620,7 +646,7 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_
 template <typename Real, int W>
 __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
                                                                   int total_items) {
-  __shared__ Real L[kLdsValues * Tile<W>::NT];
+  __shared__ Real L[kFusedValues * Tile<W>::NT];
   const int G = gridDim.x;
   for (int base = 0; base < total_items; base += G) {
     const int it = base + xcd_tile(blockIdx.x, G);
@@ -1058,8 +1084,8 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
 // FP64 (split march, 512 threads): 132 KB of LDS, one block per compute
-// unit; FP32 (256 threads): 40 KB of LDS, two blocks per compute unit (its
-// registers allow two waves per SIMD).
+// unit; FP32 (256 threads): 44 KB of LDS, three blocks per compute unit
+// (168 registers, three waves per SIMD).
 constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }

@@ -282,6 +282,12 @@ def test_torch_buffers_and_view():
 
 @pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
 def test_batch_equals_single_boxes(method):
+    """FP32 boxes stepped in one batched launch equal the same boxes stepped
+    alone: LBE bit for bit (the batched kernel runs the same per-cell code);
+    DUGKS to FP32 rounding, since its batched kernel is a separate
+    instantiation of the tile march in which the compiler may contract
+    multiply-adds differently (a few ulps after three steps; bound 1e-6 of
+    the largest value)."""
     sizes = [8, 12, 5, 16]
     states = [synth.random_populations(n, seed=40 + i) for i, n in enumerate(sizes)]
     singles = []
@@ -296,7 +302,10 @@ def test_batch_equals_single_boxes(method):
             b.set_populations(f)
         dhit.step_boxes(boxes, 3)
         for b, ref in zip(boxes, singles):
-            np.testing.assert_array_equal(b.get_populations(), ref)
+            if method == "dugks":
+                np.testing.assert_allclose(b.get_populations(), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+            else:
+                np.testing.assert_array_equal(b.get_populations(), ref)
             assert b.steps == 3
     finally:
         for b in boxes:
@@ -313,7 +322,8 @@ def test_batch_graph_replays_equal_single_boxes(method, precision):
     per-cell code), DUGKS populations to rounding (the batched and the
     single-box kernels are separate instantiations of the same tile code,
     whose floating-point contraction may differ), global sums of every step
-    within the FP64 bar."""
+    within the FP64 bar (for FP32 DUGKS within 1e-6: they are FP64 sums of
+    populations that may differ by a few ulps)."""
     sizes = [8, 12, 5, 16, 24]
     states = [synth.random_populations(n, seed=70 + i, amplitude=0.01) for i, n in enumerate(sizes)]
     ref_boxes = [dhit.Box(n, method, precision, 0.01) for n in sizes]
@@ -340,7 +350,8 @@ def test_batch_graph_replays_equal_single_boxes(method, precision):
                     assert b.steps == rb.steps == 8 * (replay + 1)
                     hb, hr = b.sums_history(8), rb.sums_history(8)
                     scale = max(np.abs(hr).max(), 1e-30)
-                    assert np.abs(hb - hr).max() <= 1e-12 * scale
+                    sums_tol = 1e-6 if (method == "dugks" and precision == "fp32") else 1e-12
+                    assert np.abs(hb - hr).max() <= sums_tol * scale
                 # eager work between replays
                 other.step(2)
                 boxes[0].moments()
