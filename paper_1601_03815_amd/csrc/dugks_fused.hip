@@ -41,7 +41,7 @@
 // Pxz, Pyz, Pzz) of planes p-2, p-1 and p: 16 + 12 + 12 values per column.
 //
 // Two marches implement this.  fused_tile (FP32): one thread per column,
-// 44 values of LDS per column (44 KB for a 32 x 8 tile, three blocks per
+// 44 values of LDS per column (44 KB for a 32 x 8 tile, two blocks per
 // compute unit).  split_tile (FP64): two threads per column, one in each of
 // two groups that hold about half of the populations each (see below), so
 // that a thread's registers fit two waves per SIMD; 66 values per column.
@@ -429,11 +429,18 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   Real *const LY = L + kLdsValues * NT + tid;
 
   Real pf[kQ];        // f~ of the plane being published (loaded one plane ahead)
-  Real acc_c[kQ];     // result of centre p-1, completed in this iteration
-  Real acc_p[kQ];     // result of centre p
+  // A centre's result is f~+ plus the stencil and face terms, which are
+  // small beside it: they are summed apart (acc) and f~+ (fp) is added once,
+  // when the centre is stored, so that the result is rounded at the scale of
+  // f~ once instead of at every term (in FP32 this more than halves the
+  // rounding noise the march adds per step).
+  Real acc_c[kQ];     // terms of centre p-1, completed in this iteration
+  Real acc_p[kQ];     // terms of centre p
+  Real fp_c[kQ];      // f~+ of centre p-1
+  Real fp_p[kQ];      // f~+ of centre p
   Real nxt[10];       // z-1 terms of the z-moving populations of centre p+1
   Real zl[4];         // lower half of the z-face above the previous plane
-  static_for<kQ>([&](auto q) { acc_p[q] = Real(0); });
+  static_for<kQ>([&](auto q) { acc_p[q] = Real(0); fp_p[q] = Real(0); });
   static_for<10>([&](auto i) { nxt[i] = Real(0); });
   static_for<4>([&](auto i) { zl[i] = Real(0); });
 
@@ -448,8 +455,12 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
     // plain (L2-allocating) stores: a tile row's 30 updated cells do not
     // fill whole 128-byte lines, and L2 merges them with the neighbouring
     // tiles' rows before they are written back
-    static_for<kQ>([&](auto q) { out[(int64_t)q * stride + cell] = acc_c[q]; });
-    sums_of_populations<Real>(acc_c, p.inv_rho0, v);
+    Real res[kQ];
+    static_for<kQ>([&](auto q) {
+      res[q] = fp_c[q] + acc_c[q];
+      out[(int64_t)q * stride + cell] = res[q];
+    });
+    sums_of_populations<Real>(res, p.inv_rho0, v);
   };
 
   load_raw<Real>(ft, stride, n, col, z0 - 1, pf);
@@ -468,16 +479,17 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
     const Plane<Real, W> c2{nullptr, nullptr, LZ + q3mm * (kNZ * NT)};              // plane p-2
 
     // centre p-1 becomes the completed centre
-    static_for<kQ>([&](auto q) { acc_c[q] = acc_p[q]; });
+    static_for<kQ>([&](auto q) { acc_c[q] = acc_p[q]; fp_c[q] = fp_p[q]; });
     // own-column pieces of plane p: z+1 terms of centre p-1, the centre
     // terms and initial value of centre p, z-1 terms of centre p+1 (formed
     // by halo columns too, which never store them)
     publish_cell<Real, W>(pf, LP, LQ + q2 * (kNQ * NT), LZ + q3 * (kNZ * NT), p, [&](auto q, Real bq, Real ftq) {
       if constexpr (kCz[q] != 0) acc_c[q] -= dtal * ((Real(0.5 * kCz[q]) - h) * bq);
-      Real r = ftq;
-      if constexpr (kCz[q] != 0) r += nxt[zslot(q)];
+      Real r = Real(0);
+      if constexpr (kCz[q] != 0) r = nxt[zslot(q)];
       if constexpr (q != 0) r -= dtal * (Real(speed2(q) == 1 ? 2 : 4) * h * bq);
       acc_p[q] = r;
+      fp_p[q] = ftq;
       if constexpr (kCz[q] != 0) nxt[zslot(q)] = -(dtal * ((Real(-0.5 * kCz[q]) - h) * bq));
     });
     __syncthreads();
@@ -610,12 +622,13 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   }
 }
 
-// Register budget of the one-thread march: in FP32 it is held to 168
-// registers, three waves per SIMD (three blocks of 44 KB of LDS per compute
-// unit); the march is still issue-bound at two, and the third wave covers
-// the LDS and memory waits.  (FP64 tiles use the split march.)
+// Register budget of the one-thread march: in FP32, 256 registers, two
+// waves per SIMD.  (Without the separate f~+ of two centres it fits 168
+// registers and three waves, 10% faster, but its rounding noise then puts
+// the FP32 spectrum's weakest resolved shells at ~1e-4 of FP64.)  FP64
+// tiles use the split march.
 template <typename Real>
-constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 3 : 1;
+constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
 
 // Tile of a block, numbered so that the blocks one XCD runs (blocks are
 // dealt to the eight XCDs in turn) take consecutive tiles: block b of a
@@ -1084,8 +1097,8 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
 // FP64 (split march, 512 threads): 132 KB of LDS, one block per compute
-// unit; FP32 (256 threads): 44 KB of LDS, three blocks per compute unit
-// (168 registers, three waves per SIMD).
+// unit; FP32 (256 threads): 44 KB of LDS, two blocks per compute unit
+// (two waves per SIMD).
 constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
