@@ -34,7 +34,11 @@
 //     populations.
 // The x- and y-faces of centre p-1 are formed in the same iteration from
 // the moment fields of planes p-2, p-1 and p, after which centre p-1 is
-// complete and stored.  Between planes a thread carries the running
+// complete and stored.  Each in-plane face is formed once, by one of its two
+// cells, and handed to the other: across lanes for the x-faces (a tile row
+// is 32 consecutive lanes) and through LDS for the y-faces (in the FP32
+// march the upper cell applies it, and is stored, after the barrier that
+// ends the iteration).  Between planes a thread carries the running
 // results of centres p and p+1 in registers.  LDS holds the populations of
 // plane p only, the in-plane moment fields (R0, Jx, Jy, Pxx, Pxy, Pyy) of
 // planes p-1 and p, and the fields the x/y-faces differentiate in z (Jz,
