@@ -171,6 +171,16 @@ def extras(torch, dhit):
                                                           for kk, vv in r.items()} for r in rep]}
             torch.cuda.empty_cache()
     out["precision"] = prec
+    # stability (Sec. IV.E): largest stable Re_lambda at 128^3, FP64, over 6000 time units
+    from paper_1601_03815_amd import stability
+    print("bench: stability", file=sys.stderr, flush=True)
+    u = synth.dhit_field(128, seed=1, k0=4, u_rms=0.05)
+    stab = {"n": 128, "horizon": 6000.0, "re_lambda_per_nu": round(stability.re_lambda(u, 1.0), 6)}
+    for method, nu_s, nu_u in (("bgk", 1e-2, 1e-3), ("mrt", 1e-3, 1e-7), ("dugks", 1e-3, 1e-8)):
+        r = stability.max_stable_re_lambda(u, method, nu_s, nu_u, 6000.0, iters=8)
+        stab[method] = {k: (round(v, 8) if isinstance(v, float) else v) for k, v in r.items() if k != "method"}
+        torch.cuda.empty_cache()
+    out["stability"] = stab
     return out
 
 

@@ -55,3 +55,20 @@ def test_fp64_spectrum_matches_oracle_over_horizon(method):
     kr = resolved_shells(n, nu, st_ref["eps"])
     np.testing.assert_allclose(E[1:kr + 1], E_ref[1:kr + 1], rtol=1e-12)
     assert abs(st["K"] / st_ref["K"] - 1) < 1e-12 and abs(st["eps"] / st_ref["eps"] - 1) < 1e-12
+
+
+def test_stability_ordering_of_the_schemes():
+    """Sec. IV.E: on one mesh the DUGKS (CFL 0.9) stays stable at Reynolds
+    numbers where the LBE blows up.  DHIT 32^3 (u' = 0.05, k0 = 4) over 1000
+    time units: BGK-LBE blows up at nu = 1e-3 where MRT-LBE and the DUGKS
+    run; MRT-LBE blows up at nu = 3e-6 where the DUGKS still runs."""
+    from paper_1601_03815_amd import stability
+    u = synth.dhit_field(32, seed=1, k0=4, u_rms=0.05)
+    assert not stability.run_stable(u, "bgk", 1e-3, 1000.0)[0]
+    assert stability.run_stable(u, "mrt", 1e-3, 1000.0)[0]
+    assert stability.run_stable(u, "dugks", 1e-3, 1000.0)[0]
+    assert not stability.run_stable(u, "mrt", 3e-6, 1000.0)[0]
+    assert stability.run_stable(u, "dugks", 3e-6, 1000.0)[0]
+    # Re_lambda of the initial field is proportional to 1/nu
+    r1, r2 = stability.re_lambda(u, 1e-3), stability.re_lambda(u, 1e-4)
+    assert abs(r2 / r1 - 10.0) < 1e-9
