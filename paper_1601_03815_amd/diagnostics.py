@@ -1,0 +1,67 @@
+"""Statistics of decaying isotropic turbulence (Sec. III) derived from the
+library's energy spectrum and its K, eps, S, F.
+
+Lattice units: cells of unit size in a periodic box of n cells, shell k
+holds the integer wavevectors with round(|k|) = k, and the physical
+wavenumber of shell k is kappa_k = 2 pi k / n (the one eps is formed with).
+
+    u'         = sqrt(<u.u>/3) = sqrt(2 K / 3)
+    lambda     = sqrt(15 nu / eps) u'          transverse Taylor microscale
+    Re_lambda  = u' lambda / nu
+    eta        = (nu^3 / eps)^(1/4)            Kolmogorov length
+    D(k)       = 2 nu kappa_k^2 E(k)           dissipation spectrum
+    kappa_max eta with kappa_max = pi (the grid's largest wavenumber, k = n/2)
+
+`DhitStatistics.record` steps a box and collects these as time series.
+"""
+import math
+
+import numpy as np
+
+
+def statistics(E, stats, nu, n):
+    """Dict of the Sec. III statistics from a spectrum E[0..kmax] and the
+    library's stats (K, eps, S, F) of an n^3 box at viscosity nu."""
+    K, eps = float(stats["K"]), float(stats["eps"])
+    up = math.sqrt(2.0 * K / 3.0)
+    lam = math.sqrt(15.0 * nu / eps) * up if eps > 0 else math.inf
+    eta = (nu ** 3 / eps) ** 0.25 if eps > 0 else math.inf
+    kappa = 2.0 * math.pi * np.arange(len(E)) / n
+    return {
+        "K": K, "eps": eps, "S": float(stats["S"]), "F": float(stats["F"]),
+        "u_rms": up, "lambda": lam, "re_lambda": up * lam / nu, "eta": eta,
+        "kmax_eta": math.pi * eta,
+        "D": 2.0 * nu * kappa ** 2 * np.asarray(E, dtype=np.float64),
+    }
+
+
+class DhitStatistics:
+    """Time series of the Sec. III statistics of one box."""
+
+    def __init__(self, box, nu):
+        self.box, self.nu = box, nu
+        self.records = []
+
+    def sample(self, time):
+        E, st = self.box.energy_spectrum()
+        rec = statistics(E, st, self.nu, self.box.n)
+        rec["t"] = float(time)
+        rec["E"] = np.asarray(E, dtype=np.float64)
+        self.records.append(rec)
+        return rec
+
+    def record(self, steps, every, dt=1.0):
+        """Samples now, then every `every` steps up to `steps` more steps
+        (dt: time per step, for the time axis)."""
+        t0 = self.box.steps * dt
+        self.sample(t0)
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            self.box.step(k)
+            done += k
+            self.sample(t0 + done * dt)
+        return self.records
+
+    def series(self, key):
+        return np.array([r["t"] for r in self.records]), np.array([r[key] for r in self.records])

@@ -1,0 +1,63 @@
+"""Sec. III statistics derived from the spectrum: closed forms on the CPU,
+a recorded DHIT time series on the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1601_03815_amd.diagnostics import statistics
+
+
+def test_single_mode_closed_forms():
+    """u = U sin(kappa y) e_x, kappa = 2 pi m / n: K = U^2/4, eps = nu kappa^2 U^2/2,
+    u' = U/sqrt(6), lambda = sqrt(5)/kappa, Re_lambda = u' lambda / nu,
+    eta = (nu^3/eps)^(1/4), and D(k) is eps in shell m, zero elsewhere."""
+    n, m, U, nu = 32, 3, 0.04, 0.01
+    kappa = 2 * math.pi * m / n
+    E = np.zeros(n // 2 + 1)
+    E[m] = U * U / 4
+    st = {"K": U * U / 4, "eps": nu * kappa ** 2 * U * U / 2, "S": 0.0, "F": 1.5}
+    r = statistics(E, st, nu, n)
+    assert r["u_rms"] == pytest.approx(U / math.sqrt(6), rel=1e-14)
+    assert r["lambda"] == pytest.approx(math.sqrt(5) / kappa, rel=1e-14)
+    assert r["re_lambda"] == pytest.approx(U / math.sqrt(6) * math.sqrt(5) / kappa / nu, rel=1e-14)
+    assert r["eta"] == pytest.approx((nu ** 3 / st["eps"]) ** 0.25, rel=1e-14)
+    assert r["kmax_eta"] == pytest.approx(math.pi * r["eta"], rel=1e-14)
+    assert r["D"][m] == pytest.approx(st["eps"], rel=1e-14)
+    assert np.count_nonzero(r["D"]) == 1
+
+
+def test_dissipation_spectrum_sums_to_eps_for_on_shell_modes():
+    """Modes whose |k| is an integer (axis modes) sit exactly on their shell,
+    so sum_k D(k) equals eps = 2 nu sum |kappa|^2 E."""
+    n, nu = 24, 0.003
+    rng = np.random.default_rng(5)
+    E = np.zeros(n // 2 + 1)
+    E[1:9] = rng.uniform(0.0, 1e-3, 8)
+    kappa = 2 * math.pi * np.arange(len(E)) / n
+    eps = 2 * nu * np.sum(kappa ** 2 * E)
+    r = statistics(E, {"K": E.sum(), "eps": eps, "S": 0.0, "F": 3.0}, nu, n)
+    assert r["D"].sum() == pytest.approx(eps, rel=1e-13)
+
+
+@pytest.mark.gpu
+def test_recorded_dhit_statistics():
+    """DHIT 32^3 (nu = 0.01, u' = 0.05, k0 = 4) over 300 MRT-LBE steps: the
+    recorder samples every 50 steps; u' matches K; the dissipation spectrum
+    sums to eps up to the shell rounding of off-axis modes; K decays, eta
+    grows after the dissipation peak, and Re_lambda falls."""
+    import paper_1601_03815_amd as dhit
+    import synth
+    from paper_1601_03815_amd.diagnostics import DhitStatistics
+    nu = 0.01
+    with dhit.Box(32, "mrt", "fp64", nu) as b:
+        b.init_velocity_field(synth.dhit_field(32, seed=4, k0=4, u_rms=0.05))
+        rec = DhitStatistics(b, nu).record(300, 50)
+    assert [r["t"] for r in rec] == [0, 50, 100, 150, 200, 250, 300]
+    for r in rec:
+        assert r["u_rms"] == pytest.approx(math.sqrt(2 * r["K"] / 3), rel=1e-14)
+        assert abs(r["D"].sum() / r["eps"] - 1) < 0.1
+    K = [r["K"] for r in rec]
+    assert all(a > b for a, b in zip(K, K[1:]))
+    assert rec[-1]["re_lambda"] < rec[0]["re_lambda"]
+    assert rec[-1]["eta"] > rec[2]["eta"]
