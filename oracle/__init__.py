@@ -298,6 +298,52 @@ def init_mrt_equilibrium(u, drho=None, rho0=1.0, w_eps=0.0, w_epsj=-475.0 / 63.0
 
 
 # ----------------------------------------------------------------------------
+# Consistent initial state, Sec. IV.A
+# ----------------------------------------------------------------------------
+
+def consistent_init(u, drho, method, nu, iters, rho0=1.0, mrt=None):
+    """Initial LBE state consistent with a prescribed velocity field
+    (Sec. IV.A: the kinetic schemes need the density fluctuation and the
+    non-equilibrium part that belong to the initial velocity; the paper
+    takes them from an iteration of the scheme with the velocity held at
+    its initial value).
+
+    Start from the method's equilibrium state E(drho, rho0 u) (drho = None
+    for zero); then, `iters` times: one LBE step of `method` (collide then
+    stream), moments (drho', j') of the new state, and
+    f <- f + E(drho', rho0 u) - E(drho', j'), which puts the momentum back
+    to rho0 u while keeping the density and the non-equilibrium part.  E is
+    f^eq (BGK) or M^-1 m^eq (MRT), the state `init_equilibrium` /
+    `init_mrt_equilibrium` build.
+
+    Returns (f, residual): the pre-collision state and the largest change
+    of drho over the last iteration (0 for iters = 0)."""
+    u = _f64(u)
+    m = dict(PAPER_MRT)
+    if mrt:
+        m.update(mrt)
+    if method == "bgk":
+        def E(d, j):
+            return init_equilibrium(j / rho0, d, rho0)
+    elif method == "mrt":
+        def E(d, j):
+            return init_mrt_equilibrium(j / rho0, d, rho0, m["w_eps"], m["w_epsj"], m["w_xx"])
+    else:
+        raise ValueError("the iteration is defined for the LBE methods")
+    j0 = rho0 * u
+    f = E(np.zeros(u.shape[1:]) if drho is None else _f64(drho), j0)
+    d_prev = moments(f, rho0)[0]
+    residual = 0.0
+    for _ in range(iters):
+        f = lbe_step(f, method, nu, rho0, mrt)
+        d, j, _s = moments(f, rho0)
+        f = f + E(d, j0) - E(d, j)
+        residual = float(np.abs(d - d_prev).max())
+        d_prev = d
+    return f, residual
+
+
+# ----------------------------------------------------------------------------
 # Spectral diagnostics, Sec. III
 # ----------------------------------------------------------------------------
 

@@ -1,6 +1,9 @@
-"""Initial pressure of Sec. IV.A (density fluctuation consistent with the
-initial velocity): closed forms on the CPU; on the GPU, the start-up
-density transient it removes."""
+"""Consistent initial state of Sec. IV.A: the spectral initial pressure and
+the LBE iteration with the velocity held at its initial value.  On the CPU,
+closed forms pin both (the oracle's iteration against the Chapman-Enskog
+non-equilibrium of a shear wave and the Taylor-Green pressure); on the GPU,
+the library's iteration against the oracle's and the start-up transient
+both remove."""
 import numpy as np
 import pytest
 
@@ -21,6 +24,47 @@ def test_pressure_of_flows_without_pressure_gradient():
     """A uniform flow and a plane shear wave carry no pressure."""
     assert np.abs(synth.initial_pressure(synth.uniform_flow(8, 0.03, -0.01, 0.02))).max() == 0.0
     assert np.abs(synth.initial_pressure(synth.shear_wave(12, 0.02, 2))).max() < 1e-18
+
+
+@pytest.mark.parametrize("method", ["bgk", "mrt"])
+@pytest.mark.parametrize("nu,iters", [(0.1, 40), (0.02, 200)])
+def test_oracle_iteration_shear_wave_non_equilibrium(method, nu, iters):
+    """Shear wave u_x = U sin(2 pi y/n): no pressure, so drho stays 0 and
+    the velocity is the prescribed one; the pre-collision non-equilibrium
+    xy moment converges to the Chapman-Enskog value
+    -tau rho0 c_s^2 (d_x u_y + d_y u_x) with tau = 3 nu + 1/2 (the shear
+    relaxation time of both collision operators, Sec. II.A / II.B).  The
+    lattice's error at kh = 2 pi/32 is 0.4%."""
+    import oracle
+    n, U = 32, 1e-3
+    c, _w = oracle.lattice()
+    u = synth.shear_wave(n, U, 1)
+    f, res = oracle.consistent_init(u, None, method, nu, iters)
+    d, j, _s = oracle.moments(f)
+    eq = oracle.init_equilibrium(j, d) if method == "bgk" else oracle.init_mrt_equilibrium(j, d)
+    pxy = np.tensordot(c[:, 0] * c[:, 1], f - eq, axes=(0, 0))
+    y = synth.grid(n)
+    tau = 3.0 * nu + 0.5
+    ref = -tau / 3.0 * U * (2.0 * np.pi / n) * np.cos(y)[None, :, None] * np.ones((n, n, n))
+    assert np.abs(pxy - ref).max() < 0.01 * np.abs(ref).max()
+    assert np.abs(d).max() < 1e-9 and np.abs(j - u).max() < 1e-15 and res < 1e-10
+
+
+@pytest.mark.parametrize("method,tol", [("bgk", 0.1), ("mrt", 0.12)])
+def test_oracle_iteration_taylor_green_pressure(method, tol):
+    """From drho = 0 the iteration converges to the Taylor-Green pressure,
+    drho = 3 p with p = rho0 U^2/16 (cos 2x + cos 2y)(cos 2z + 2), up to
+    the lattice's error at 16^3 (7-9% at kh = 2 (2 pi/16)), with zero mean."""
+    import oracle
+    n, U = 16, 0.02
+    x = synth.grid(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    p = U * U / 16 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)
+    f, res = oracle.consistent_init(synth.taylor_green(n, U), None, method, 0.05, 300)
+    d = oracle.moments(f)[0]
+    assert res < 1e-15
+    assert np.abs(d - 3 * p).max() < tol * np.abs(3 * p).max()
+    assert abs(d.mean()) < 1e-15
 
 
 def _divergence_rms(j):
