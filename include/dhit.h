@@ -50,7 +50,7 @@ enum dhit_status {
     DHIT_EINVAL = -1,      /* bad argument (null pointer, size or parameter out of range) */
     DHIT_ENOMEM = -2,      /* device or host allocation failed */
     DHIT_EDEVICE = -3,     /* a HIP or hipFFT call failed */
-    DHIT_EMETHOD = -4,     /* step_lbe on a DUGKS box or step_dugks on an LBE box */
+    DHIT_EMETHOD = -4,     /* step_lbe or init_consistent on a DUGKS box, step_dugks on an LBE box */
     DHIT_ENONFINITE = -5   /* a global reduction became NaN or infinite (the run blew up) */
 };
 
@@ -128,6 +128,27 @@ int32_t destroy_box(dhit_box *b);
  * starts from f = M^-1 m^eq (the fixed point of its collision, Sec. II.B).
  * Resets the step counter and the reduction history.  Synchronous. */
 int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
+
+/* Consistent initial state of an LBE box for a prescribed velocity field
+ * (Sec. IV.A: the kinetic schemes start from the density fluctuation and
+ * the non-equilibrium part that belong to the initial velocity, found by
+ * iterating the scheme with the velocity held at its initial value).
+ * Starts as init_velocity_field(b, u, drho) (drho: host, NULL = 0; the
+ * spectral pressure of the velocity is the natural first guess), then runs
+ * `iters` passes of: one LBE step of the box's method, then every cell's
+ * momentum put back to rho0 u with its density and non-equilibrium part
+ * kept (f += E(drho, rho0 u) - E(drho, j), E the state init_velocity_field
+ * builds).  On return the velocity is u (to rounding), the density and the
+ * non-equilibrium part are the scheme's own, and the step counter and the
+ * reduction history are reset.  *residual (host, may be NULL) receives the
+ * largest change of drho over the last pass (0 for iters = 0).
+ * u: host [3][n^3] doubles, idx = (z*n + y)*n + x.  Synchronous; allocates
+ * device work space for the call.  DHIT_EMETHOD on a DUGKS box (with the
+ * finite-volume fluxes the held-velocity iteration does not converge; start
+ * a DUGKS box from the spectral pressure with init_velocity_field),
+ * DHIT_EINVAL for a null u or iters < 0, DHIT_ENONFINITE if the density
+ * stopped being finite. */
+int32_t init_consistent(dhit_box *b, const double *u, const double *drho, int32_t iters, double *residual);
 
 /* Advance an LBE box by nsteps >= 0 steps of dt = 1: fused pull
  * streaming + collision (Sec. II.B evolution equation; BGK or MRT).  The

@@ -79,6 +79,7 @@ def _load():
         "create_box": ([P, ctypes.POINTER(ctypes.c_void_p)], i32),
         "destroy_box": ([box], i32),
         "init_velocity_field": ([box, dp, dp], i32),
+        "init_consistent": ([box, dp, dp, i32, dp], i32),
         "step_lbe": ([box, i32], i32),
         "step_dugks": ([box, i32], i32),
         "moments": ([box, dp, dp, dp], i32),
@@ -173,6 +174,16 @@ def init_velocity_field(h, n, u, drho=None):
     u = _f64_in(u, (3, n, n, n))
     d = None if drho is None else _f64_in(drho, (n, n, n))
     _check(_lib.init_velocity_field(h, _ptr(u), _ptr(d)))
+
+
+def init_consistent(h, n, u, drho=None, iters=0):
+    """Consistent initial state of an LBE box; returns the largest change
+    of drho over the last pass."""
+    u = _f64_in(u, (3, n, n, n))
+    d = None if drho is None else _f64_in(drho, (n, n, n))
+    res = np.zeros(1, dtype=np.float64)
+    _check(_lib.init_consistent(h, _ptr(u), _ptr(d), int(iters), _ptr(res)))
+    return float(res[0])
 
 
 def step_lbe(h, nsteps=1):
@@ -282,7 +293,7 @@ def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
 
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
-    "init_velocity_field", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum",
+    "init_velocity_field", "init_consistent", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",

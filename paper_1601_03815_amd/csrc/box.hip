@@ -1,11 +1,13 @@
 // C ABI of the library (declared in include/dhit.h): parameter handling,
 // box lifetime, buffers, and the step loops.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lattice.hpp"
 #include "runtime.hpp"
@@ -280,6 +282,69 @@ int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho) {
     }
     (void)hipFree(du);
     if (dr) (void)hipFree(dr);
+    b->steps = 0;
+    return DHIT_OK;
+  });
+}
+
+int32_t init_consistent(dhit_box *b, const double *u, const double *drho, int32_t iters, double *residual) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!u) fail(DHIT_EINVAL, "null velocity field");
+    if (iters < 0) fail(DHIT_EINVAL, "iters must be >= 0");
+    if (b->p.method == DHIT_DUGKS)
+      fail(DHIT_EMETHOD, "init_consistent is defined for LBE boxes; start a DUGKS box with init_velocity_field");
+    const size_t bytes = (size_t)b->ncell * sizeof(double);
+    const int blocks = dhit::cell_blocks(b->ncell);
+    double *du = nullptr, *dr = nullptr, *dprev = nullptr, *dmax = nullptr;
+    auto cleanup = [&]() {
+      (void)hipStreamSynchronize(b->stream);
+      if (du) (void)hipFree(du);
+      if (dr) (void)hipFree(dr);
+      if (dprev) (void)hipFree(dprev);
+      if (dmax) (void)hipFree(dmax);
+    };
+    try {
+      if (hipMalloc(&du, 3 * bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+      if (drho && hipMalloc(&dr, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+      if (iters > 0 && (hipMalloc(&dprev, bytes) != hipSuccess ||
+                        hipMalloc(&dmax, (size_t)blocks * sizeof(double)) != hipSuccess))
+        fail(DHIT_ENOMEM, "cannot allocate iteration buffers");
+      DHIT_HIP(hipMemcpyAsync(du, u, 3 * bytes, hipMemcpyHostToDevice, b->stream));
+      if (drho) DHIT_HIP(hipMemcpyAsync(dr, drho, bytes, hipMemcpyHostToDevice, b->stream));
+      b->cur = 0;
+      dhit::launch_init_equilibrium(*b, du, dr, b->f[0]);
+      if (iters > 0) {
+        // drho before the first pass is the initial field (the equilibrium state carries it exactly)
+        if (dr)
+          DHIT_HIP(hipMemcpyAsync(dprev, dr, bytes, hipMemcpyDeviceToDevice, b->stream));
+        else
+          DHIT_HIP(hipMemsetAsync(dprev, 0, bytes, b->stream));
+      }
+      for (int32_t k = 0; k < iters; ++k) {
+        const bool last = k == iters - 1;
+        double *slot = b->hist + (k % dhit::kHistoryCap) * 5;
+        dhit::launch_lbe_step(*b, b->f[b->cur], b->f[1 - b->cur], slot);
+        b->cur = 1 - b->cur;
+        dhit::launch_hold_velocity(*b, b->f[b->cur], du, last ? nullptr : dprev, last ? dprev : nullptr,
+                                   last ? dmax : nullptr);
+      }
+      double res = 0.0;
+      if (iters > 0) {
+        std::vector<double> h(blocks);
+        DHIT_HIP(hipMemcpyAsync(h.data(), dmax, (size_t)blocks * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        DHIT_HIP(hipStreamSynchronize(b->stream));
+        for (double v : h) res = std::max(res, v);
+      }
+      DHIT_HIP(hipStreamSynchronize(b->stream));
+      if (!std::isfinite(res)) fail(DHIT_ENONFINITE, "initial-state iteration produced a non-finite density");
+      if (residual) *residual = res;
+    } catch (...) {
+      cleanup();
+      b->steps = 0;
+      throw;
+    }
+    cleanup();
     b->steps = 0;
     return DHIT_OK;
   });

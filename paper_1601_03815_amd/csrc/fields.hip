@@ -23,6 +23,61 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const double *__restrict__
   static_for<kQ>([&](auto q) { f[(int64_t)q * p.stride + cell] = fe[q]; });
 }
 
+// One pass of the initial-state iteration of an LBE box (Sec. IV.A: the
+// kinetic schemes start from the density fluctuation and non-equilibrium
+// part that belong to the initial velocity, found by running the scheme
+// with the velocity held at its initial value).  After each time step, every
+// cell's momentum is put back to rho0 u while its density and its
+// non-equilibrium part are kept: f += E(drho, rho0 u) - E(drho, j), with E
+// the state init_kernel builds.  Both collisions conserve drho and j and
+// relax only f - E, so the update gives the same result on the stored
+// post-collision state as on the pre-collision one.
+// drho_out (optional) receives drho; with drho_prev and block_max given,
+// block b stores the largest |drho - drho_prev| of its cells in block_max[b].
+template <typename Real, bool Mrt>
+__global__ __launch_bounds__(kBlock) void hold_velocity_kernel(Real *__restrict__ f, const double *__restrict__ u,
+                                                               double *__restrict__ drho_out,
+                                                               const double *__restrict__ drho_prev,
+                                                               double *__restrict__ block_max, StepParams p,
+                                                               int ncell) {
+  __shared__ double wave_max[kWaves];
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  double dev = 0.0;
+  if (cell < ncell) {
+    Real g[kQ];
+    static_for<kQ>([&](auto q) { g[q] = f[(int64_t)q * p.stride + cell]; });
+    Real r, jx, jy, jz;
+    cell_moments<Real>(g, r, jx, jy, jz);
+    const Real hx = Real(p.rho0 * u[cell]);
+    const Real hy = Real(p.rho0 * u[(int64_t)ncell + cell]);
+    const Real hz = Real(p.rho0 * u[2 * (int64_t)ncell + cell]);
+    Real held[kQ], now[kQ];
+    if constexpr (Mrt) {
+      mrt_equilibrium_populations<Real>(r, hx, hy, hz, p, held);
+      mrt_equilibrium_populations<Real>(r, jx, jy, jz, p, now);
+    } else {
+      equilibrium<Real>(r, hx, hy, hz, Real(p.rho0), Real(p.inv_rho0), held);
+      equilibrium<Real>(r, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), now);
+    }
+    static_for<kQ>([&](auto q) { f[(int64_t)q * p.stride + cell] = g[q] + (held[q] - now[q]); });
+    if (drho_out) drho_out[cell] = (double)r;
+    if (drho_prev) {
+      dev = fabs((double)r - drho_prev[cell]);
+      if (!(dev < INFINITY)) dev = INFINITY;  // a NaN must survive the fmax reduction
+    }
+  }
+  if (!block_max) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_down(dev, off, 64));
+  if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wave_max[0];
+    for (int w = 1; w < kWaves; ++w) m = fmax(m, wave_max[w]);
+    block_max[blockIdx.x] = m;
+  }
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void moments_kernel(const Real *__restrict__ f, double *__restrict__ drho,
                                                          double *__restrict__ j, StepParams p, int ncell,
@@ -145,6 +200,31 @@ void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drh
     else
       hipLaunchKernelGGL((init_kernel<float, false>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
                          static_cast<float *>(dst), b.sp, (int)b.ncell);
+  }
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_hold_velocity(dhit_box &b, void *f, const double *d_u, double *d_drho_out, const double *d_drho_prev,
+                          double *d_block_max) {
+  const int blocks = cell_blocks(b.ncell);
+  const bool mrt = b.p.method == DHIT_LBE_MRT;
+  const int n = (int)b.ncell;
+  if (b.p.precision == DHIT_FP64) {
+    double *g = static_cast<double *>(f);
+    if (mrt)
+      hipLaunchKernelGGL((hold_velocity_kernel<double, true>), dim3(blocks), dim3(kBlock), 0, b.stream, g, d_u,
+                         d_drho_out, d_drho_prev, d_block_max, b.sp, n);
+    else
+      hipLaunchKernelGGL((hold_velocity_kernel<double, false>), dim3(blocks), dim3(kBlock), 0, b.stream, g, d_u,
+                         d_drho_out, d_drho_prev, d_block_max, b.sp, n);
+  } else {
+    float *g = static_cast<float *>(f);
+    if (mrt)
+      hipLaunchKernelGGL((hold_velocity_kernel<float, true>), dim3(blocks), dim3(kBlock), 0, b.stream, g, d_u,
+                         d_drho_out, d_drho_prev, d_block_max, b.sp, n);
+    else
+      hipLaunchKernelGGL((hold_velocity_kernel<float, false>), dim3(blocks), dim3(kBlock), 0, b.stream, g, d_u,
+                         d_drho_out, d_drho_prev, d_block_max, b.sp, n);
   }
   DHIT_HIP(hipGetLastError());
 }

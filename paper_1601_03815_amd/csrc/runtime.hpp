@@ -122,6 +122,11 @@ void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_ou
 int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk);
 void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst);
 void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
+// One pass of the LBE initial-state iteration on state f (in place): momentum
+// back to rho0 u, density and non-equilibrium kept; optional drho output and
+// per-block largest |drho - drho_prev| (cell_blocks(ncell) entries).
+void launch_hold_velocity(dhit_box &b, void *f, const double *d_u, double *d_drho_out, const double *d_drho_prev,
+                          double *d_block_max);
 void launch_pack(dhit_box &b, const void *f, double *d_out);     // state -> [19][ncell] double
 void launch_unpack(dhit_box &b, const double *d_in, void *f);    // [19][ncell] double -> state
 void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out);
