@@ -411,3 +411,24 @@ def energy_spectrum(u, nu, kmax=None):
     stats = dict(K=K, eps=eps, S=S, F=F, u_rms=float(u_rms), lam=float(lam),
                  eta=float(eta), re_lam=float(u_rms * lam / nu))
     return E, stats
+
+
+def vorticity(u):
+    """Vorticity omega = curl u of a velocity field u[3, n, n, n] in lattice
+    units (cell size 1), by spectral differentiation: omega_hat = i kappa x
+    u_hat with kappa = 2 pi k / n, the Nyquist component of each derivative
+    dropped as for S and F (Sec. IV.B shows the vorticity magnitude of the
+    flow fields).  Returns omega[3, n, n, n]."""
+    u = np.asarray(u, dtype=np.float64)
+    n = u.shape[1]
+    k1 = wavenumbers(n)
+    if n % 2 == 0:
+        k1 = np.where(np.abs(k1) == n // 2, 0.0, k1)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    kap = [2.0 * np.pi / n * kx, 2.0 * np.pi / n * ky, 2.0 * np.pi / n * kz]
+    uh = np.fft.fftn(u, axes=(1, 2, 3))
+
+    def d(comp, axis):
+        return np.real(np.fft.ifftn(1j * kap[axis] * uh[comp]))
+
+    return np.stack([d(2, 1) - d(1, 2), d(0, 2) - d(2, 0), d(1, 0) - d(0, 1)])

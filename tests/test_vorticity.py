@@ -1,0 +1,39 @@
+"""Vorticity of the velocity field (the flow fields of Sec. IV.B): the
+oracle's spectral curl against closed forms on the CPU; the library's
+against the oracle on the GPU."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def test_oracle_vorticity_taylor_green_closed_form():
+    """Taylor-Green vortex in lattice units (X = 2 pi x/n, d/dx = (2 pi/n) d/dX):
+    omega = (2 pi/n) U (-cos X sin Y sin Z, -sin X cos Y sin Z, 2 sin X sin Y cos Z)."""
+    import oracle
+    n, U = 16, 0.05
+    x = synth.grid(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    a = 2 * np.pi / n * U
+    ref = np.stack([-a * np.cos(X) * np.sin(Y) * np.sin(Z), -a * np.sin(X) * np.cos(Y) * np.sin(Z),
+                    2 * a * np.sin(X) * np.sin(Y) * np.cos(Z)])
+    w = oracle.vorticity(synth.taylor_green(n, U))
+    assert np.abs(w - ref).max() < 1e-15
+
+
+@pytest.mark.parametrize("n", [15, 16])
+def test_oracle_vorticity_enstrophy_and_divergence(n):
+    """Solenoidal periodic field: <|omega|^2> = eps / nu (eps of the
+    spectrum, Sec. III) and div omega = 0; a uniform flow has none."""
+    import oracle
+    nu = 0.01
+    u = synth.dhit_field(n, seed=7, k0=2, u_rms=0.05)
+    w = oracle.vorticity(u)
+    _E, st = oracle.energy_spectrum(u, nu)
+    assert abs(np.mean(np.sum(w * w, axis=0)) - st["eps"] / nu) < 1e-12 * st["eps"] / nu
+    wh = np.fft.fftn(w, axes=(1, 2, 3))
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    div = kx * wh[0] + ky * wh[1] + kz * wh[2]
+    assert np.abs(div).max() < 1e-12 * np.abs(wh).max()
+    assert np.abs(oracle.vorticity(synth.uniform_flow(n, 0.03, -0.02, 0.01))).max() < 1e-17
