@@ -187,6 +187,14 @@ int32_t sums_history(dhit_box *b, double *out, int32_t count);
  * Allocates its work space on the first call.  Synchronous. */
 int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats);
 
+/* Vorticity omega = curl u of the current velocity field u = j/rho0 (the
+ * flow fields shown in Sec. IV.B), in lattice units (cell size 1): spectral
+ * derivatives, omega_hat = i kappa x u_hat with kappa = 2 pi k / n, the
+ * Nyquist component of each derivative dropped as for S and F.
+ * omega: host [3][n^3] doubles, idx = (z*n + y)*n + x.  Shares the
+ * spectrum work space (allocated on the first call).  Synchronous. */
+int32_t vorticity(dhit_box *b, double *omega);
+
 /* Copy the stored population field to/from host f[19][n^3] (double; FP32
  * boxes convert).  The stored phase is post-collision for LBE boxes and
  * f~ for DUGKS boxes.  set_populations resets the step counter and the

@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     DUGKS, FP32, FP64, LBE_BGK, LBE_MRT, METHODS, PRECISIONS, VARIANT_DEFAULT, VARIANT_TWO_PASS,
     DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, last_error,
-    moments, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
+    moments, vorticity, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
     create_batch, batch_step, batch_info, destroy_batch,
 )
@@ -111,6 +111,11 @@ class Box:
         if kmax is None:
             kmax = self.n // 2
         return energy_spectrum(self.handle, kmax)
+
+    def vorticity(self):
+        """Vorticity of the current velocity field, (3, n, n, n) doubles in
+        lattice units."""
+        return vorticity(self.handle, self.n)
 
     def get_populations(self):
         return get_populations(self.handle, self.n)

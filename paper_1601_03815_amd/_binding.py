@@ -85,6 +85,7 @@ def _load():
         "moments": ([box, dp, dp, dp], i32),
         "sums_history": ([box, dp, i32], i32),
         "energy_spectrum": ([box, dp, i32, dp], i32),
+        "vorticity": ([box, dp], i32),
         "get_populations": ([box, dp], i32),
         "set_populations": ([box, dp], i32),
         "steps_taken": ([box], i64),
@@ -216,6 +217,13 @@ def energy_spectrum(h, kmax):
     return E, dict(K=st[0], eps=st[1], S=st[2], F=st[3])
 
 
+def vorticity(h, n):
+    """omega = curl(j/rho0) as (3, n, n, n) doubles."""
+    w = _f64_out((3, n, n, n))
+    _check(_lib.vorticity(h, _ptr(w)))
+    return w
+
+
 def get_populations(h, n):
     f = _f64_out((Q, n, n, n))
     _check(_lib.get_populations(h, _ptr(f)))
@@ -293,7 +301,7 @@ def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
 
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
-    "init_velocity_field", "init_consistent", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum",
+    "init_velocity_field", "init_consistent", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",

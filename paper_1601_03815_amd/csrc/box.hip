@@ -431,6 +431,15 @@ int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats) {
   });
 }
 
+int32_t vorticity(dhit_box *b, double *omega) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!omega) fail(DHIT_EINVAL, "null output");
+    dhit::vorticity_compute(*b, omega);
+    return DHIT_OK;
+  });
+}
+
 int32_t get_populations(dhit_box *b, double *f) {
   return guarded([&]() -> int32_t {
     require_box(b);

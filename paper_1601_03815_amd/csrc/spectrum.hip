@@ -88,6 +88,31 @@ __global__ __launch_bounds__(256) void deriv_kernel(const hipfftDoubleComplex *_
   out[m] = o;
 }
 
+// Component a of the vorticity on the half spectrum, scaled by `scale`:
+// out = scale i (kappa_b u_hat_c - kappa_c u_hat_b), (a, b, c) cyclic; the
+// Nyquist wavenumber of each derivative direction is set to zero, as in
+// deriv_kernel.
+__global__ __launch_bounds__(256) void curl_kernel(const hipfftDoubleComplex *__restrict__ uh,
+                                                   hipfftDoubleComplex *__restrict__ out, int n, int64_t nhalf,
+                                                   int a, double scale) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nhalf) return;
+  const int nxh = n / 2 + 1;
+  const int64_t r = m / nxh;
+  int k[3] = {(int)(m % nxh), signed_k((int)(r % n), n), signed_k((int)(r / n), n)};
+  for (int i = 0; i < 3; ++i)
+    if ((n % 2 == 0) && (2 * k[i] == n || 2 * k[i] == -n)) k[i] = 0;
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const double kb = 2.0 * M_PI / n * k[b], kc = 2.0 * M_PI / n * k[c];
+  const hipfftDoubleComplex ub = uh[(int64_t)b * nhalf + m], uc = uh[(int64_t)c * nhalf + m];
+  // i (kb uc - kc ub)
+  const double re = kb * uc.x - kc * ub.x, im = kb * uc.y - kc * ub.y;
+  hipfftDoubleComplex o;
+  o.x = -im * scale;
+  o.y = re * scale;
+  out[m] = o;
+}
+
 // Sums of d^2, d^3, d^4 of a real field scaled by `scale`.
 __global__ __launch_bounds__(kBlock) void power_sums_kernel(const double *__restrict__ d, int64_t ncell, double scale,
                                                             double *__restrict__ partials) {
@@ -192,6 +217,25 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
   }
   for (int i = 0; i < 15; ++i)
     if (!std::isfinite(ds[i])) throw Error(DHIT_ENONFINITE, "velocity field is not finite");
+}
+
+void vorticity_compute(dhit_box &b, double *omega_host) {
+  ensure_work(b);
+  SpectrumWork &w = *b.spec;
+  const int n = b.n;
+  DHIT_FFT(hipfftSetStream(w.fwd, b.stream));
+  DHIT_FFT(hipfftSetStream(w.inv, b.stream));
+  launch_velocity(b, b.f[b.cur], w.u);
+  DHIT_FFT(hipfftExecD2Z(w.fwd, w.u, w.uh));
+  const double inv_n3 = 1.0 / ((double)n * n * n);  // both transforms are unnormalised
+  const int blocks = (int)((w.nhalf + 255) / 256);
+  for (int a = 0; a < 3; ++a) {
+    hipLaunchKernelGGL(curl_kernel, dim3(blocks), dim3(256), 0, b.stream, w.uh, w.tmp, n, w.nhalf, a, inv_n3);
+    DHIT_HIP(hipGetLastError());
+    DHIT_FFT(hipfftExecZ2D(w.inv, w.tmp, w.u + (int64_t)a * b.ncell));
+  }
+  DHIT_HIP(hipMemcpyAsync(omega_host, w.u, 3 * b.ncell * sizeof(double), hipMemcpyDeviceToHost, b.stream));
+  DHIT_HIP(hipStreamSynchronize(b.stream));
 }
 
 }  // namespace dhit

@@ -12,7 +12,13 @@ wavenumber of shell k is kappa_k = 2 pi k / n (the one eps is formed with).
     D(k)       = 2 nu kappa_k^2 E(k)           dissipation spectrum
     kappa_max eta with kappa_max = pi (the grid's largest wavenumber, k = n/2)
 
-`DhitStatistics.record` steps a box and collects these as time series.
+Normalisations of Sec. IV.A and IV.B: time in eddy-turnover units
+t' = t eps0 / K0 (t0 = K0/eps0 of the initial field), velocity magnitude
+|u| / u'0 and vorticity magnitude |omega| L / u'0 with L = n, the box size
+in lattice units.
+
+`DhitStatistics.record` steps a box and collects these as time series;
+`normalized_slices` gives the two magnitude fields on a plane z = const.
 """
 import math
 
@@ -47,6 +53,9 @@ class DhitStatistics:
         rec = statistics(E, st, self.nu, self.box.n)
         rec["t"] = float(time)
         rec["E"] = np.asarray(E, dtype=np.float64)
+        first = self.records[0] if self.records else rec
+        # eddy-turnover time of the first sample
+        rec["t_prime"] = (rec["t"] - first["t"]) * first["eps"] / first["K"] if first["K"] > 0 else 0.0
         self.records.append(rec)
         return rec
 
@@ -65,3 +74,16 @@ class DhitStatistics:
 
     def series(self, key):
         return np.array([r["t"] for r in self.records]), np.array([r[key] for r in self.records])
+
+
+def normalized_slices(box, u0_rms, z=None):
+    """|u| / u'0 and |omega| L / u'0 (L = n) on the plane z (default n/2, the
+    plane z = L/2 of the paper's figures), as two (n, n) arrays indexed [y, x].
+    The velocity comes from the box's moments and the vorticity from its
+    spectral curl."""
+    n = box.n
+    z = n // 2 if z is None else int(z)
+    _d, j, _s = box.moments()
+    u = j[:, z] / box.params.rho0
+    w = box.vorticity()[:, z]
+    return np.sqrt(np.sum(u * u, axis=0)) / u0_rms, np.sqrt(np.sum(w * w, axis=0)) * n / u0_rms

@@ -61,3 +61,47 @@ def test_recorded_dhit_statistics():
     assert all(a > b for a, b in zip(K, K[1:]))
     assert rec[-1]["re_lambda"] < rec[0]["re_lambda"]
     assert rec[-1]["eta"] > rec[2]["eta"]
+
+
+class _FakeBox:
+    """Stands in for a box: a fixed sequence of spectra, one per sample."""
+
+    def __init__(self, stats, n=16):
+        self.n, self._stats, self._i, self.steps = n, stats, 0, 0
+
+    def energy_spectrum(self):
+        st = self._stats[self._i]
+        self._i += 1
+        return np.array([0.0, st["K"]]), st
+
+    def step(self, k):
+        self.steps += k
+
+
+def test_eddy_turnover_time():
+    """t' = t eps0 / K0 with K0, eps0 of the first sample (Sec. IV.A)."""
+    from paper_1601_03815_amd.diagnostics import DhitStatistics
+    sts = [{"K": 2e-3, "eps": 4e-6, "S": 0.0, "F": 3.0}, {"K": 1.5e-3, "eps": 5e-6, "S": 0.0, "F": 3.0},
+           {"K": 1e-3, "eps": 3e-6, "S": 0.0, "F": 3.0}]
+    rec = DhitStatistics(_FakeBox(sts), 0.01).record(200, 100, dt=0.5)
+    assert [r["t"] for r in rec] == [0.0, 50.0, 100.0]
+    assert [r["t_prime"] for r in rec] == pytest.approx([0.0, 0.1, 0.2], rel=1e-14)
+
+
+@pytest.mark.gpu
+def test_normalized_slices_taylor_green():
+    """Taylor-Green vortex on the plane z = L/2 (Z = pi): |u| / U =
+    sqrt(sin^2 X cos^2 Y + cos^2 X sin^2 Y) and |omega| L / U =
+    2 pi sqrt(cos^2 X sin^2 Y sin^2 Z + ... ) = 4 pi |sin X sin Y| there."""
+    import paper_1601_03815_amd as dhit
+    import synth
+    from paper_1601_03815_amd.diagnostics import normalized_slices
+    n, U = 16, 0.05
+    x = synth.grid(n)
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    with dhit.Box(n, "bgk", "fp64", 0.01) as b:
+        b.init_velocity_field(synth.taylor_green(n, U))
+        su, sw = normalized_slices(b, U)
+    ref_u = np.sqrt(np.sin(X) ** 2 * np.cos(Y) ** 2 + np.cos(X) ** 2 * np.sin(Y) ** 2)
+    assert np.abs(su - ref_u).max() < 1e-13
+    assert np.abs(sw - 4 * np.pi * np.abs(np.sin(X) * np.sin(Y))).max() < 1e-11
