@@ -50,6 +50,7 @@ def _lib():
             "oracle_dugks_transform": ([p, p, p, i32, d, d, d], None),
             "oracle_dugks_step": ([p, p, i32, d, d, d], None),
             "oracle_dugks_cells": ([p, i32, d, d, d, p, i64, p], None),
+            "oracle_dugks_step_mesh": ([p, p, i32, p, d, d, d], None),
             "oracle_lbe_pull_cells": ([p, i32, i32, d, p, d, d, d, d, p, i64, p], None),
             "oracle_moments": ([p, i32, d, p, p, p], None),
             "oracle_init_equilibrium": ([p, i32, p, p, d], None),
@@ -248,6 +249,23 @@ def dugks_step(ft, nu=None, dt=0.5, rho0=1.0, nsteps=1, tau=None):
     out = np.empty_like(ft)
     for _ in range(nsteps):
         _lib().oracle_dugks_step(_ptr(cur), _ptr(out), _n_of(ft), tau, dt, rho0)
+        cur, out = out, cur
+    return cur
+
+
+def dugks_step_mesh(ft, widths, nu=None, dt=0.5, rho0=1.0, nsteps=1, tau=None):
+    """`nsteps` DUGKS steps on a stretched periodic mesh: widths[a][i] is
+    the width of cell i along axis a (x, y, z).  With unit widths this is
+    `dugks_step`."""
+    ft = _f64(ft)
+    n = _n_of(ft)
+    W = _f64(widths, (3, n))
+    if tau is None:
+        tau = tau_dugks(nu)
+    cur = ft.copy()
+    out = np.empty_like(ft)
+    for _ in range(nsteps):
+        _lib().oracle_dugks_step_mesh(_ptr(cur), _ptr(out), n, _ptr(W), tau, dt, rho0)
         cur, out = out, cur
     return cur
 

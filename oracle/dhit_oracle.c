@@ -380,6 +380,114 @@ void oracle_dugks_step(const double *ft, double *out, int32_t n, double tau,
     free(ftp);
 }
 
+/* ------------------------------------------------------------------ */
+/* DUGKS on a stretched (non-uniform, tensor-product) periodic mesh     */
+/* ------------------------------------------------------------------ */
+
+/* Geometry of one axis from its n cell widths w[0..n-1] (periodic):
+ * the centre of cell i sits at c_i = w_0/2 + sum_{k<i} (w_k + w_{k+1})/2 and
+ * its faces at c_i -/+ w_i/2.  Distances between centres wrap around. */
+static double centre_gap(const double *w, int64_t n, int64_t i) /* c_{i+1} - c_i */
+{
+    return 0.5 * (w[wrap(i, n)] + w[wrap(i + 1, n)]);
+}
+
+/* Distribution f at the centre of the face between cell L = (x,y,z) and
+ * R = L + e_d at t_n + h on the mesh with widths W[3][n] (Sec. II.A, the
+ * one-dimensional interpolation formulas applied along the face normal):
+ *   sigma_d = (fbp_R - fbp_L) / (c_R - c_L),
+ *   fbp(x_b) = fbp_L + sigma_d (x_b - c_L), x_b - c_L = w_L / 2;
+ * tangential derivatives: the central difference of each adjacent cell,
+ * (fbp(+e_t) - fbp(-e_t)) / (c_{k+1} - c_{k-1}), interpolated linearly to
+ * the face with the same weight as the value (on a uniform mesh: their
+ * mean); then fbar = fbp(x_b) - h xi . sigma, face moments, f^eq, and
+ * f = 2tau/(2tau+h) fbar + h/(2tau+h) f^eq. */
+static void face_distribution_mesh(const double *fbp, int64_t n, const double *W, int64_t x, int64_t y,
+                                   int64_t z, int d, double tau, double h, double rho0, double *fb)
+{
+    int64_t ncell = n * n * n;
+    int64_t e[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    int64_t pos[3] = {x, y, z};
+    int64_t L = cell_index(x, y, z, n);
+    int64_t R = cell_index(x + e[d][0], y + e[d][1], z + e[d][2], n);
+    const double *wd = W + d * n;
+    double gap = centre_gap(wd, n, pos[d]);   /* c_R - c_L */
+    double half = 0.5 * wd[wrap(pos[d], n)];   /* x_b - c_L */
+    double lam = half / gap;                    /* interpolation weight of R */
+    double fbar[Q];
+    for (int q = 0; q < Q; q++) {
+        double fl = fbp[q * ncell + L], fr = fbp[q * ncell + R];
+        double sigma[3];
+        for (int t = 0; t < 3; t++) {
+            if (t == d) {
+                sigma[t] = (fr - fl) / gap;
+            } else {
+                const double *wt = W + t * n;
+                int64_t k = pos[t];
+                double span = centre_gap(wt, n, k - 1) + centre_gap(wt, n, k); /* c_{k+1} - c_{k-1} */
+                int64_t Lp = cell_index(x + e[t][0], y + e[t][1], z + e[t][2], n);
+                int64_t Lm = cell_index(x - e[t][0], y - e[t][1], z - e[t][2], n);
+                int64_t Rp = cell_index(x + e[d][0] + e[t][0], y + e[d][1] + e[t][1], z + e[d][2] + e[t][2], n);
+                int64_t Rm = cell_index(x + e[d][0] - e[t][0], y + e[d][1] - e[t][1], z + e[d][2] - e[t][2], n);
+                double gL = (fbp[q * ncell + Lp] - fbp[q * ncell + Lm]) / span;
+                double gR = (fbp[q * ncell + Rp] - fbp[q * ncell + Rm]) / span;
+                sigma[t] = gL + lam * (gR - gL);
+            }
+        }
+        double at_face = fl + sigma[d] * half;
+        double xs = CX[q] * sigma[0] + CY[q] * sigma[1] + CZ[q] * sigma[2];
+        fbar[q] = at_face - h * xs;
+    }
+    double r = 0, jx = 0, jy = 0, jz = 0, feq[Q];
+    for (int q = 0; q < Q; q++) {
+        r += fbar[q];
+        jx += CX[q] * fbar[q];
+        jy += CY[q] * fbar[q];
+        jz += CZ[q] * fbar[q];
+    }
+    oracle_feq(r, jx, jy, jz, rho0, feq);
+    for (int q = 0; q < Q; q++)
+        fb[q] = 2.0 * tau / (2.0 * tau + h) * fbar[q] + h / (2.0 * tau + h) * feq[q];
+}
+
+/* One DUGKS step on the stretched mesh W[3][n] (cell widths per axis):
+ * f~^{n+1} = f~+ - dt/|V| sum over the six faces of (xi . n) f_face A,
+ * |V| = w_x w_y w_z of the cell, A the face's area (product of the two
+ * tangential widths). */
+void oracle_dugks_step_mesh(const double *ft, double *out, int32_t n, const double *W /* [3][n] */,
+                            double tau, double dt, double rho0)
+{
+    int64_t ncell = (int64_t)n * n * n;
+    double h = 0.5 * dt;
+    double *fbp = (double *)malloc(sizeof(double) * Q * ncell);
+    double *ftp = (double *)malloc(sizeof(double) * Q * ncell);
+    oracle_dugks_transform(ft, fbp, ftp, n, tau, dt, rho0);
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < n; z++)
+        for (int64_t y = 0; y < n; y++)
+            for (int64_t x = 0; x < n; x++) {
+                double w[3] = {W[x], W[n + y], W[2 * n + z]};
+                double vol = w[0] * w[1] * w[2];
+                double flux[Q];
+                for (int q = 0; q < Q; q++) flux[q] = 0;
+                for (int d = 0; d < 3; d++) {
+                    double area = vol / w[d];
+                    double fplus[Q], fminus[Q];
+                    face_distribution_mesh(fbp, n, W, x, y, z, d, tau, h, rho0, fplus);
+                    face_distribution_mesh(fbp, n, W, x - (d == 0), y - (d == 1), z - (d == 2), d, tau, h, rho0,
+                                           fminus);
+                    for (int q = 0; q < Q; q++) {
+                        double xn = (d == 0) ? CX[q] : (d == 1) ? CY[q] : CZ[q];
+                        flux[q] += xn * (fplus[q] - fminus[q]) * area;
+                    }
+                }
+                int64_t idx = cell_index(x, y, z, n);
+                for (int q = 0; q < Q; q++) out[q * ncell + idx] = ftp[q * ncell + idx] - dt / vol * flux[q];
+            }
+    free(fbp);
+    free(ftp);
+}
+
 /* DUGKS update of selected cells only, for checks at sizes where a whole
  * oracle step is too slow.  The update of a cell reads f-bar-plus only at
  * offsets inside the 3x3x3 cube around it (every face uses L, R and their

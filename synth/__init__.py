@@ -127,3 +127,30 @@ def ensemble_grids(count=64, choices=(32, 48, 64, 96), seed=0):
     """Grid sizes of a batched ensemble, drawn uniformly from `choices`."""
     rng = np.random.default_rng(seed)
     return [int(c) for c in rng.choice(np.asarray(choices), size=count)]
+
+
+def stretched_widths(n, amp=(0.2, 0.3, 0.25), phase=(0.0, 0.7, 1.9)):
+    """Cell widths of a smoothly stretched periodic mesh, one row per axis:
+    w_i = 1 + a cos(2 pi (i + 1/2)/n + phase), so that the box length stays
+    n on every axis and the widths vary by a factor (1 + a)/(1 - a)."""
+    i = np.arange(n) + 0.5
+    return np.stack([1.0 + a * np.cos(2.0 * np.pi * i / n + ph) for a, ph in zip(amp, phase)])
+
+
+def cell_centres(w):
+    """Centres of the cells of one axis with widths w: c_0 = w_0/2,
+    c_i = c_{i-1} + (w_{i-1} + w_i)/2."""
+    w = np.asarray(w, dtype=np.float64)
+    return np.concatenate([[0.0], np.cumsum(0.5 * (w[:-1] + w[1:]))]) + 0.5 * w[0]
+
+
+def shear_wave_on_mesh(widths, u0=1e-3, mode=1):
+    """u_x = U0 sin(2 pi mode y / L) at the cell centres of a stretched mesh
+    (L = sum of the y widths), v = w = 0."""
+    widths = np.asarray(widths, dtype=np.float64)
+    n = widths.shape[1]
+    yc = cell_centres(widths[1])
+    L = widths[1].sum()
+    u = np.zeros((3, n, n, n))
+    u[0] = u0 * np.sin(2.0 * np.pi * mode * yc / L)[None, :, None]
+    return u
