@@ -50,7 +50,7 @@ enum dhit_status {
     DHIT_EINVAL = -1,      /* bad argument (null pointer, size or parameter out of range) */
     DHIT_ENOMEM = -2,      /* device or host allocation failed */
     DHIT_EDEVICE = -3,     /* a HIP or hipFFT call failed */
-    DHIT_EMETHOD = -4,     /* step_lbe or init_consistent on a DUGKS box, step_dugks on an LBE box */
+    DHIT_EMETHOD = -4,     /* a call that does not apply to the box's method or mesh */
     DHIT_ENONFINITE = -5   /* a global reduction became NaN or infinite (the run blew up) */
 };
 
@@ -128,6 +128,29 @@ int32_t destroy_box(dhit_box *b);
  * starts from f = M^-1 m^eq (the fixed point of its collision, Sec. II.B).
  * Resets the step counter and the reduction history.  Synchronous. */
 int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
+
+/* Stretched mesh for a DUGKS box (the finite-volume scheme's advantage the
+ * paper names in Sec. V; the reconstruction of Sec. II.A with the positions
+ * of a non-uniform mesh).  widths: host [3][n] doubles, the width of cell i
+ * along x, y, z (the box length of an axis is the sum of its widths; the
+ * mesh is periodic).  Faces sit at c_i +- w_i/2, with cell centres
+ * c_i = w_0/2 + sum_{k<i} (w_k + w_{k+1})/2.  At each face between cells L
+ * and R the value is fbp_L + (fbp_R - fbp_L) w_L/(w_L + w_R), the normal
+ * gradient (fbp_R - fbp_L)/(c_R - c_L), and each tangential gradient is the
+ * cells' central difference over c_{k+1} - c_{k-1}, interpolated with the
+ * same weight; the update divides each axis's flux difference by the cell's
+ * width along it.  From then on every step of the box runs this path
+ * (whatever the variant) and the five sums of the step history and of
+ * moments() are weighted by the cell volumes w_x w_y w_z.  Unit widths give
+ * the uniform scheme.  widths = NULL returns the box to unit cells.
+ * Allocates the mesh tables and, if the box has none, the scratch field of
+ * the two-pass form.  Synchronous.  DHIT_EMETHOD on an LBE box;
+ * DHIT_EINVAL for a width that is not finite and > 0, or for
+ * sqrt(2) dt > min width (CFL above 1; the paper takes
+ * dt = CFL dx_min / sqrt(2)).  Boxes with a stretched mesh cannot be batched
+ * (a batch built before the call keeps stepping them on unit cells), and
+ * energy_spectrum and vorticity reject them (DHIT_EMETHOD). */
+int32_t set_mesh(dhit_box *b, const double *widths);
 
 /* Consistent initial state of an LBE box for a prescribed velocity field
  * (Sec. IV.A: the kinetic schemes start from the density fluctuation and

@@ -9,7 +9,7 @@ the library is missing, importing this package raises ImportError.
 from ._binding import (  # noqa: F401
     DUGKS, FP32, FP64, LBE_BGK, LBE_MRT, METHODS, PRECISIONS, VARIANT_DEFAULT, VARIANT_TWO_PASS,
     DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
-    default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, last_error,
+    default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, set_mesh, last_error,
     moments, vorticity, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
     create_batch, batch_step, batch_info, destroy_batch,
@@ -87,6 +87,11 @@ class Box:
     # verbs ------------------------------------------------------------------
     def init_velocity_field(self, u, drho=None):
         init_velocity_field(self.handle, self.n, u, drho)
+
+    def set_mesh(self, widths=None):
+        """DUGKS boxes: cell widths (3, n) per axis of a stretched periodic
+        mesh (None: unit cells).  The step sums become volume-weighted."""
+        set_mesh(self.handle, self.n, widths)
 
     def init_consistent(self, u, drho=None, iters=50):
         """LBE boxes: start from (u, drho) and iterate the scheme with the

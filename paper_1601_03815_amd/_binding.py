@@ -80,6 +80,7 @@ def _load():
         "destroy_box": ([box], i32),
         "init_velocity_field": ([box, dp, dp], i32),
         "init_consistent": ([box, dp, dp, i32, dp], i32),
+        "set_mesh": ([box, dp], i32),
         "step_lbe": ([box, i32], i32),
         "step_dugks": ([box, i32], i32),
         "moments": ([box, dp, dp, dp], i32),
@@ -175,6 +176,13 @@ def init_velocity_field(h, n, u, drho=None):
     u = _f64_in(u, (3, n, n, n))
     d = None if drho is None else _f64_in(drho, (n, n, n))
     _check(_lib.init_velocity_field(h, _ptr(u), _ptr(d)))
+
+
+def set_mesh(h, n, widths=None):
+    """Stretched mesh of a DUGKS box: widths (3, n) cell widths per axis, or
+    None for unit cells."""
+    w = None if widths is None else _f64_in(widths, (3, n))
+    _check(_lib.set_mesh(h, _ptr(w)))
 
 
 def init_consistent(h, n, u, drho=None, iters=0):
@@ -301,7 +309,7 @@ def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
 
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
-    "init_velocity_field", "init_consistent", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity",
+    "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",

@@ -253,6 +253,7 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
       throw dhit::Error(DHIT_EINVAL, "all boxes of a batch must share method and precision");
     if (boxes[i]->p.method == DHIT_DUGKS && boxes[i]->p.variant != DHIT_VARIANT_DEFAULT)
       throw dhit::Error(DHIT_EINVAL, "batched DUGKS uses the fused kernel (variant default)");
+    if (boxes[i]->mesh) throw dhit::Error(DHIT_EINVAL, "boxes with a stretched mesh cannot be batched");
     for (int32_t j = 0; j < i; ++j)
       if (boxes[j] == boxes[i]) throw dhit::Error(DHIT_EINVAL, "a box appears twice in a batch");
   }

@@ -255,6 +255,7 @@ int32_t destroy_box(dhit_box *b) {
   if (b->partials) (void)hipFree(b->partials);
   if (b->hist) (void)hipFree(b->hist);
   if (b->scratch) (void)hipFree(b->scratch);
+  if (b->mesh) (void)hipFree(b->mesh);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return DHIT_OK;
@@ -283,6 +284,48 @@ int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho) {
     (void)hipFree(du);
     if (dr) (void)hipFree(dr);
     b->steps = 0;
+    return DHIT_OK;
+  });
+}
+
+int32_t set_mesh(dhit_box *b, const double *widths) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (b->p.method != DHIT_DUGKS) fail(DHIT_EMETHOD, "set_mesh applies to DUGKS boxes");
+    DHIT_HIP(hipStreamSynchronize(b->stream));
+    if (!widths) {
+      if (b->mesh) (void)hipFree(b->mesh);
+      b->mesh = nullptr;
+      return DHIT_OK;
+    }
+    const int n = b->n;
+    double wmin = INFINITY;
+    for (int i = 0; i < 3 * n; ++i) {
+      if (!(widths[i] > 0.0) || !std::isfinite(widths[i])) fail(DHIT_EINVAL, "cell widths must be finite and > 0");
+      wmin = std::min(wmin, widths[i]);
+    }
+    // the fastest particles move sqrt(2) per unit time: CFL = sqrt(2) dt / w_min
+    if (std::sqrt(2.0) * b->p.dt > wmin) fail(DHIT_EINVAL, "dt exceeds CFL 1 on the smallest cell");
+    std::vector<double> t((size_t)3 * dhit::kMeshTables * n);
+    for (int a = 0; a < 3; ++a) {
+      const double *w = widths + (size_t)a * n;
+      double *row = t.data() + (size_t)a * dhit::kMeshTables * n;
+      for (int i = 0; i < n; ++i) {
+        const double wm = w[(i + n - 1) % n], wi = w[i], wp = w[(i + 1) % n];
+        row[dhit::kMeshWidth * n + i] = wi;
+        row[dhit::kMeshInvWidth * n + i] = 1.0 / wi;
+        row[dhit::kMeshLam * n + i] = wi / (wi + wp);
+        row[dhit::kMeshInvGap * n + i] = 2.0 / (wi + wp);
+        row[dhit::kMeshInvSpan * n + i] = 1.0 / (0.5 * wm + wi + 0.5 * wp);
+      }
+    }
+    if (!b->scratch) {
+      const int64_t bytes = population_buffer_bytes(&b->p);
+      if (hipMalloc(&b->scratch, (size_t)bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
+    }
+    if (!b->mesh && hipMalloc(&b->mesh, t.size() * sizeof(double)) != hipSuccess)
+      fail(DHIT_ENOMEM, "cannot allocate mesh tables");
+    DHIT_HIP(hipMemcpy(b->mesh, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
     return DHIT_OK;
   });
 }
@@ -426,6 +469,7 @@ int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats) {
   return guarded([&]() -> int32_t {
     require_box(b);
     if (kmax < 0 || !E) fail(DHIT_EINVAL, "need E and kmax >= 0");
+    if (b->mesh) fail(DHIT_EMETHOD, "spectral diagnostics need unit cells (this box has a stretched mesh)");
     dhit::spectrum_compute(*b, E, kmax, stats);
     return DHIT_OK;
   });
@@ -435,6 +479,7 @@ int32_t vorticity(dhit_box *b, double *omega) {
   return guarded([&]() -> int32_t {
     require_box(b);
     if (!omega) fail(DHIT_EINVAL, "null output");
+    if (b->mesh) fail(DHIT_EMETHOD, "spectral diagnostics need unit cells (this box has a stretched mesh)");
     dhit::vorticity_compute(*b, omega);
     return DHIT_OK;
   });

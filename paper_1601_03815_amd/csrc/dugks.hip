@@ -15,6 +15,15 @@
 // faces of each cell from that field (through the caches) and writes the
 // update.  It follows the face-by-face description directly and serves as a
 // cross-check of the fused kernel (dugks_fused.hip), which is the default.
+//
+// It also holds the stretched-mesh form (set_mesh): the same two passes
+// with the reconstruction written for cell widths w that vary along each
+// axis (Sec. II.A's interpolation with x_b - x_L = w_L/2 and the gradient
+// over c_R - c_L; tangential central differences over c_{k+1} - c_{k-1},
+// interpolated to the face with the value's weight):
+//   fbar = fbp_L + lam sd - h [xi_d sd / gap + sum_t xi_t (G_t(L) + lam (G_t(R) - G_t(L))) / span_t],
+//   lam = w_L/(w_L + w_R), gap = (w_L + w_R)/2, sd = fbp_R - fbp_L,
+// and the update f~(t+dt) = f~+ - dt sum_d xi_d (f_face(+d) - f_face(-d)) / w_d.
 #include "collision.hpp"
 
 namespace dhit {
@@ -130,6 +139,131 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
 }
 
+// Face at side S of the cell along axis D on a stretched mesh; adds
+// S xi_D f_face / w_D(cell) to acc.  pos = the cell's (x, y, z).
+template <int D, int S, typename Real>
+__device__ __forceinline__ void face_accumulate_mesh(const Real *__restrict__ fbp, int cell, const Nbr &nb,
+                                                     const int (&pos)[3], const double *__restrict__ mesh,
+                                                     const StepParams &p, Real (&acc)[kQ]) {
+  const int64_t stride = p.stride;
+  const int n = p.n;
+  constexpr int l = (S == -1) ? -1 : 0;
+  constexpr int r = l + 1;
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  auto off = [&](int a, int tb, int tc) {
+    int d[3] = {0, 0, 0};
+    d[D] = a;
+    d[T1] = tb;
+    d[T2] = tc;
+    return nb.at(d[0], d[1], d[2]);
+  };
+  auto table = [&](int axis, int t, int i) { return mesh[((int64_t)axis * kMeshTables + t) * n + i]; };
+  const int iL = (S == -1) ? (pos[D] == 0 ? n - 1 : pos[D] - 1) : pos[D];
+  const Real lam = Real(table(D, kMeshLam, iL)), inv_gap = Real(table(D, kMeshInvGap, iL));
+  const Real inv_span1 = Real(table(T1, kMeshInvSpan, pos[T1]));
+  const Real inv_span2 = Real(table(T2, kMeshInvSpan, pos[T2]));
+  const Real inv_w = Real(table(D, kMeshInvWidth, pos[D]));
+  const Real h = Real(p.h);
+  Real fbar[kQ];
+  static_for<kQ>([&](auto q) {
+    const Real *fq = fbp + (int64_t)q * stride + cell;
+    const Real fl = fq[off(l, 0, 0)], fr = fq[off(r, 0, 0)];
+    const Real sd = fr - fl;
+    Real tang = Real(0);
+    if constexpr (cdir(q, T1) != 0) {
+      const Real gl = fq[off(l, 1, 0)] - fq[off(l, -1, 0)], gr = fq[off(r, 1, 0)] - fq[off(r, -1, 0)];
+      tang += Real(cdir(q, T1)) * (inv_span1 * (gl + lam * (gr - gl)));
+    }
+    if constexpr (cdir(q, T2) != 0) {
+      const Real gl = fq[off(l, 0, 1)] - fq[off(l, 0, -1)], gr = fq[off(r, 0, 1)] - fq[off(r, 0, -1)];
+      tang += Real(cdir(q, T2)) * (inv_span2 * (gl + lam * (gr - gl)));
+    }
+    fbar[q] = (fl + lam * sd) - h * (Real(cdir(q, D)) * (sd * inv_gap) + tang);
+  });
+  Real drho, jx, jy, jz, feq[kQ];
+  cell_moments<Real>(fbar, drho, jx, jy, jz);
+  equilibrium<Real>(drho, jx, jy, jz, Real(p.rho0), Real(p.inv_rho0), feq);
+  const Real al = Real(p.alpha), be = Real(p.beta);
+  static_for<kQ>([&](auto q) {
+    if constexpr (cdir(q, D) != 0) {
+      const Real ff = (al * fbar[q] + be * feq[q]) * inv_w;
+      if constexpr (S * cdir(q, D) > 0) acc[q] += ff;
+      else acc[q] -= ff;
+    }
+  });
+}
+
+// Face kernel of the stretched mesh; the five sums are weighted by the
+// cell volumes w_x w_y w_z.
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void dugks_mesh_face_kernel(const Real *__restrict__ ft,
+                                                                 const Real *__restrict__ fbp, Real *__restrict__ out,
+                                                                 StepParams p, int ncell,
+                                                                 const double *__restrict__ mesh,
+                                                                 double *__restrict__ partials) {
+  const int n = p.n;
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  if (cell < ncell) {
+    const int x = cell % n;
+    const int t = cell / n;
+    const int y = t % n;
+    const int z = t / n;
+    const int pos[3] = {x, y, z};
+    const AxisOff ox = axis_offsets(x, n, 1), oy = axis_offsets(y, n, n), oz = axis_offsets(z, n, n * n);
+    Nbr nb;
+    nb.X[0] = ox.dn; nb.X[1] = 0; nb.X[2] = ox.up;
+    nb.Y[0] = oy.dn; nb.Y[1] = 0; nb.Y[2] = oy.up;
+    nb.Z[0] = oz.dn; nb.Z[1] = 0; nb.Z[2] = oz.up;
+    Real acc[kQ];
+    static_for<kQ>([&](auto q) { acc[q] = Real(0); });
+    face_accumulate_mesh<0, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    face_accumulate_mesh<0, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    face_accumulate_mesh<1, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    face_accumulate_mesh<1, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    face_accumulate_mesh<2, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    face_accumulate_mesh<2, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    const int64_t stride = p.stride;
+    const Real dt = Real(p.dt);
+    Real o[kQ];
+    static_for<kQ>([&](auto q) {
+      const Real bp = fbp[(int64_t)q * stride + cell];
+      const Real tl = ft[(int64_t)q * stride + cell];
+      o[q] = (bp + (bp - tl) * Real(1.0 / 3.0)) - dt * acc[q];
+      out[(int64_t)q * stride + cell] = o[q];
+    });
+    double c[kNumSums] = {0, 0, 0, 0, 0};
+    sums_of_populations<Real>(o, p.inv_rho0, c);
+    const double vol = mesh[(0 * kMeshTables + kMeshWidth) * n + x] * mesh[(1 * kMeshTables + kMeshWidth) * n + y] *
+                       mesh[(2 * kMeshTables + kMeshWidth) * n + z];
+    static_for<kNumSums>([&](auto i) { v[i] = vol * c[i]; });
+  }
+  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+}
+
+template <typename Real>
+static void dugks_mesh_two_pass(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  const int blocks = cell_blocks(b.ncell);
+  const Real *s = static_cast<const Real *>(src);
+  Real *d = static_cast<Real *>(dst);
+  Real *bp = static_cast<Real *>(b.scratch);
+  {
+    TimedLaunch t(b, DHIT_K_DUGKS_TRANSFORM);
+    hipLaunchKernelGGL((dugks_transform_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, b.sp,
+                       (int)b.ncell);
+    DHIT_HIP(hipGetLastError());
+    t.done();
+  }
+  {
+    TimedLaunch t(b, DHIT_K_DUGKS_FACE);
+    hipLaunchKernelGGL((dugks_mesh_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
+                       (int)b.ncell, b.mesh, b.partials);
+    DHIT_HIP(hipGetLastError());
+    t.done();
+  }
+  launch_finalize_sums(b, b.partials, blocks, sums_out);
+}
+
 template <typename Real>
 static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums_out) {
   const int blocks = cell_blocks(b.ncell);
@@ -154,6 +288,13 @@ static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums
 }
 
 void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  if (b.mesh) {
+    if (b.p.precision == DHIT_FP64)
+      dugks_mesh_two_pass<double>(b, src, dst, sums_out);
+    else
+      dugks_mesh_two_pass<float>(b, src, dst, sums_out);
+    return;
+  }
   if (b.p.variant == DHIT_VARIANT_DEFAULT) {
     launch_dugks_fused(b, src, dst, sums_out);
     return;

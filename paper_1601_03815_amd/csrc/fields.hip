@@ -78,9 +78,12 @@ __global__ __launch_bounds__(kBlock) void hold_velocity_kernel(Real *__restrict_
   }
 }
 
+// Moments of every cell and the five global sums (weighted by the cell
+// volumes w_x w_y w_z when a stretched mesh is given).
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void moments_kernel(const Real *__restrict__ f, double *__restrict__ drho,
                                                          double *__restrict__ j, StepParams p, int ncell,
+                                                         const double *__restrict__ mesh,
                                                          double *__restrict__ partials) {
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   double v[kNumSums] = {0, 0, 0, 0, 0};
@@ -96,6 +99,13 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const Real *__restrict_
       j[2 * (int64_t)ncell + cell] = (double)jz;
     }
     sums_of_cell<Real>(r, jx, jy, jz, p.inv_rho0, v);
+    if (mesh) {
+      const int n = p.n, x = cell % n, y = (cell / n) % n, z = cell / (n * n);
+      const double vol = mesh[(0 * kMeshTables + kMeshWidth) * n + x] *
+                         mesh[(1 * kMeshTables + kMeshWidth) * n + y] *
+                         mesh[(2 * kMeshTables + kMeshWidth) * n + z];
+      static_for<kNumSums>([&](auto i) { v[i] *= vol; });
+    }
   }
   write_block_partials(v, partials, gridDim.x, blockIdx.x);
 }
@@ -233,10 +243,10 @@ void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, dou
   const int blocks = cell_blocks(b.ncell);
   if (b.p.precision == DHIT_FP64)
     hipLaunchKernelGGL((moments_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream,
-                       static_cast<const double *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.partials);
+                       static_cast<const double *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.mesh, b.partials);
   else
     hipLaunchKernelGGL((moments_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream,
-                       static_cast<const float *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.partials);
+                       static_cast<const float *>(f), d_drho, d_j, b.sp, (int)b.ncell, b.mesh, b.partials);
   DHIT_HIP(hipGetLastError());
   launch_finalize_sums(b, b.partials, blocks, d_sums);
 }

@@ -44,6 +44,13 @@ struct StepParams {
 
 constexpr int kHistoryCap = 4096;
 
+// Geometry tables of a stretched DUGKS mesh (set_mesh), laid out
+// [axis][table][n] doubles; for cell i of an axis with widths w:
+//   width w_i, 1/w_i; for the face between i and i+1: lam = w_i/(w_i + w_{i+1})
+//   (position of the face between the two centres) and 1/(c_{i+1} - c_i)
+//   = 2/(w_i + w_{i+1}); 1/(c_{i+1} - c_{i-1}) for the central difference.
+enum MeshTable { kMeshWidth = 0, kMeshInvWidth, kMeshLam, kMeshInvGap, kMeshInvSpan, kMeshTables };
+
 // One box of a batched launch (device-resident table entry).  `cur` and
 // `step` live on the device so that a captured graph can be replayed for
 // any number of steps: the per-box finalisation writes the history slot of
@@ -104,6 +111,7 @@ struct dhit_box {
   double *hist = nullptr;      // [kHistoryCap][5]
   int64_t steps = 0;
   void *scratch = nullptr;     // DUGKS two-pass transform field
+  double *mesh = nullptr;      // stretched-mesh tables [3][kMeshTables][n] (DUGKS), NULL = unit cells
   dhit::StepParams sp{};
   dhit::SpectrumWork *spec = nullptr;
   dhit::KernelTimer *timer = nullptr;

@@ -109,3 +109,131 @@ def test_oracle_mesh_shear_wave_second_order():
         errs.append(abs(-np.log(amp(g) / amp(g1)) / (s2 * dt) / (nu * kap * kap) - 1))
     assert errs[1] < 0.05, errs
     assert 3.3 < errs[0] / errs[1] < 6.0, errs
+
+
+def _volumes(W):
+    return W[0][None, None, :] * W[1][None, :, None] * W[2][:, None, None]
+
+
+def _weighted_sums(f, W):
+    import oracle as O
+    d, j, _ = O.moments(f)
+    V = _volumes(W)
+    return np.array([(V * d).sum(), (V * j[0]).sum(), (V * j[1]).sum(), (V * j[2]).sum(),
+                     0.5 * (V * np.sum(j * j, axis=0)).sum()])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [5, 12, 17, 32])
+def test_mesh_step_parity_fp64(n):
+    """Two steps from a random state on a stretched mesh, element by
+    element within 1e-12 of the oracle, with the volume-weighted sums of the
+    step history and of moments()."""
+    import oracle as O
+    import paper_1601_03815_amd as dhit
+    W = synth.stretched_widths(n, AMP)
+    nu, dt = 0.02, 0.6 * W.min() / np.sqrt(2.0)
+    f0 = synth.random_populations(n, seed=300 + n, amplitude=0.01)
+    with dhit.Box(n, "dugks", "fp64", nu, dt=dt) as b:
+        b.set_mesh(W)
+        b.set_populations(f0)
+        b.step(2)
+        got = b.get_populations()
+        hist = b.sums_history(2)
+        _d, _j, sums = b.moments(want_fields=False)
+    f1 = O.dugks_step_mesh(f0, W, nu=nu, dt=dt)
+    ref = O.dugks_step_mesh(f1, W, nu=nu, dt=dt)
+    assert _rel(got, ref) <= 1e-12
+    scale = np.abs(f0).sum() * W.max() ** 3
+    assert np.abs(hist[0] - _weighted_sums(f1, W)).max() <= 1e-12 * scale
+    assert np.abs(hist[1] - _weighted_sums(ref, W)).max() <= 1e-12 * scale
+    assert np.abs(sums - _weighted_sums(ref, W)).max() <= 1e-12 * scale
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [5, 16])
+def test_mesh_step_parity_fp32(n):
+    import oracle as O
+    import paper_1601_03815_amd as dhit
+    W = synth.stretched_widths(n, AMP)
+    nu, dt = 0.02, 0.6 * W.min() / np.sqrt(2.0)
+    f0 = synth.random_populations(n, seed=400 + n, amplitude=0.01).astype(np.float32).astype(np.float64)
+    with dhit.Box(n, "dugks", "fp32", nu, dt=dt) as b:
+        b.set_mesh(W)
+        b.set_populations(f0)
+        b.step(1)
+        got = b.get_populations()
+    assert _rel(got, O.dugks_step_mesh(f0, W, nu=nu, dt=dt)) <= 2e-6
+
+
+@pytest.mark.gpu
+def test_mesh_shear_wave_second_order_on_the_gpu():
+    """The shear-wave decay rate on the stretched mesh at 16^3 and 32^3
+    (sizes the oracle takes a minute for): second-order convergence, the
+    oracle's 16^3 error reproduced."""
+    import oracle as O
+    import paper_1601_03815_amd as dhit
+    nu, U = 0.1, 1e-3
+    errs = []
+    for n in (16, 32):
+        W = synth.stretched_widths(n, AMP)
+        dt = 0.9 * W.min() / np.sqrt(2.0)
+        L = float(n)
+        kap = 2 * np.pi / L
+        T = 0.4 / (nu * kap * kap)
+        s1 = int(round(T / 4 / dt))
+        s2 = int(round(T / dt)) - s1
+        sn = np.sin(2 * np.pi * synth.cell_centres(W[1]) / L)
+        with dhit.Box(n, "dugks", "fp64", nu, dt=dt) as b:
+            b.set_mesh(W)
+            b.init_velocity_field(synth.shear_wave_on_mesh(W, U))
+            b.step(s1)
+            a1 = 2.0 / L * np.sum(W[1] * b.moments()[1][0].mean(axis=(0, 2)) * sn)
+            b.step(s2)
+            a2 = 2.0 / L * np.sum(W[1] * b.moments()[1][0].mean(axis=(0, 2)) * sn)
+        errs.append(abs(-np.log(a2 / a1) / (s2 * dt) / (nu * kap * kap) - 1))
+    assert abs(errs[0] - 0.03419) < 1e-4, errs
+    assert 3.3 < errs[0] / errs[1] < 6.0, errs
+
+
+@pytest.mark.gpu
+def test_mesh_validation_and_reset():
+    """Errors: an LBE box, a width <= 0 or not finite, CFL above 1; a mesh
+    box in a batch and in the spectral diagnostics.  set_mesh(None) returns
+    the box to the uniform scheme (same state as a box that never had a
+    mesh), and unit widths give the uniform scheme."""
+    import oracle as O
+    import paper_1601_03815_amd as dhit
+    n = 8
+    W = synth.stretched_widths(n, AMP)
+    dt = 0.6 * W.min() / np.sqrt(2.0)
+    with dhit.Box(n, "mrt", "fp64", 0.01) as lbe:
+        with pytest.raises(dhit.DhitError) as e:
+            lbe.set_mesh(W)
+        assert e.value.code == -4
+    f0 = synth.random_populations(n, seed=500, amplitude=0.01)
+    with dhit.Box(n, "dugks", "fp64", 0.02, dt=dt) as b, dhit.Box(n, "dugks", "fp64", 0.02, dt=dt) as c:
+        for bad in (np.where(np.arange(3 * n).reshape(3, n) == 5, 0.0, W), np.where(W > 1.2, np.nan, W),
+                    W * (dt * np.sqrt(2.0) / W.min()) * 0.99):
+            with pytest.raises(dhit.DhitError) as e:
+                b.set_mesh(bad)
+            assert e.value.code == -1
+        b.set_mesh(W)
+        with pytest.raises(dhit.DhitError) as e:
+            b.energy_spectrum()
+        assert e.value.code == -4
+        with pytest.raises(dhit.DhitError) as e:
+            b.vorticity()
+        assert e.value.code == -4
+        with pytest.raises(dhit.DhitError):
+            dhit.step_batch([b.handle, c.handle], 1)
+        b.set_mesh(np.ones((3, n)))
+        b.set_populations(f0)
+        b.step(1)
+        assert _rel(b.get_populations(), O.dugks_step(f0, nu=0.02, dt=dt)) <= 1e-12
+        b.set_mesh(None)
+        b.set_populations(f0)
+        c.set_populations(f0)
+        b.step(1)
+        c.step(1)
+        assert np.array_equal(b.get_populations(), c.get_populations())
