@@ -116,17 +116,55 @@ def cpu_baseline(n, nu, u256):
             "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4)}
 
 
-def extras(torch, dhit):
-    """Ensemble (64 FP32 boxes), serving (bounded Poisson trace) and FP32-vs-FP64
-    precision reports."""
+def mesh_costs(torch, dhit, n=256, steps=10, warmup=3):
+    """DUGKS on a stretched mesh against unit cells at n^3: per-kernel mean
+    launch times (HIP events on the box's stream) of the stretched-mesh
+    two-pass path and of the fused uniform kernel, same field and dt
+    (CFL 0.9 on the smallest cell of the mesh)."""
+    import numpy as np
+    import synth
+    u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
+    W = synth.stretched_widths(n)
+    dt = 0.9 * W.min() / np.sqrt(2.0)
+    out = {"n": n, "widths": "1 + a cos(2 pi (i + 1/2)/n + phase), a = (0.2, 0.3, 0.25)", "dt": round(dt, 6)}
+    for precision in ("fp64", "fp32"):
+        for label, mesh in (("uniform_fused", None), ("stretched_two_pass", W)):
+            print("bench: mesh %s %s" % (precision, label), file=sys.stderr, flush=True)
+            b = dhit.Box(n, "dugks", precision, 0.01, dt=dt, stream=torch.cuda.Stream())
+            if mesh is not None:
+                b.set_mesh(mesh)
+            b.init_velocity_field(u)
+            time_steps([b], warmup, torch)
+            dhit.set_kernel_timing(b.handle, True)
+            ms = time_steps([b], steps, torch)
+            kt = {k: round(t / c, 4) for k, (t, c) in dhit.read_kernel_timings(b.handle).items() if c}
+            dhit.set_kernel_timing(b.handle, False)
+            out["%s/%s" % (precision, label)] = {"ms_per_step": round(ms / steps, 4),
+                                                  "mlups": round(n ** 3 * steps / (ms * 1e-3) / 1e6, 1),
+                                                  "kernel_mean_ms": kt}
+            b.close()
+            torch.cuda.empty_cache()
+    return out
+
+
+def extras(torch, dhit, sections="all"):
+    """Ensemble (64 FP32 boxes), serving (bounded Poisson trace), FP32-vs-FP64
+    precision, stability and stretched-mesh reports; `sections` is 'all' or
+    a comma list of their names."""
     import synth
     from paper_1601_03815_amd import ensemble, precision, serve
+    want = set(("ensemble", "serving", "precision", "stability", "mesh") if sections == "all"
+               else sections.split(","))
     out = {}
+    if "mesh" in want:
+        out["mesh"] = mesh_costs(torch, dhit)
+    if not want & {"ensemble", "serving", "precision", "stability"}:
+        return out
     # batched ensemble: 64 realisations, grids from {32, 48, 64, 96}, FP32, nu = 0.01
-    sizes = synth.ensemble_grids(64, (32, 48, 64, 96), seed=0)
+    sizes = synth.ensemble_grids(64, (32, 48, 64, 96), seed=0) if "ensemble" in want else []
     cells = sum(n ** 3 for n in sizes)
     ens = {"boxes": 64, "cells": cells, "grid_counts": {str(n): sizes.count(n) for n in sorted(set(sizes))}}
-    for method in ("mrt", "dugks"):
+    for method in (("mrt", "dugks") if "ensemble" in want else ()):
         print("bench: ensemble %s" % method, file=sys.stderr, flush=True)
         stream = torch.cuda.Stream()
         boxes = ensemble.make_ensemble(sizes, method, "fp32", 0.01, stream=stream,
@@ -145,10 +183,11 @@ def extras(torch, dhit):
         for b in boxes:
             b.close()
         torch.cuda.empty_cache()
-    out["ensemble"] = ens
+    if "ensemble" in want:
+        out["ensemble"] = ens
     # serving: bounded trace, FP32, two HBM budgets
     srv = {}
-    for label, budget, count in (("full_hbm", 250e9, 40), ("budget_16GB", 16e9, 40)):
+    for label, budget, count in ((("full_hbm", 250e9, 40), ("budget_16GB", 16e9, 40)) if "serving" in want else ()):
         print("bench: serving %s" % label, file=sys.stderr, flush=True)
         trace = serve.poisson_trace(count, 20.0, seed=7)
         be = serve.GpuBackend(precision="fp32", nu=0.01)
@@ -157,10 +196,11 @@ def extras(torch, dhit):
         st["offered_rate_per_s"] = 20.0
         srv[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         torch.cuda.empty_cache()
-    out["serving"] = srv
+    if "serving" in want:
+        out["serving"] = srv
     # precision: FP32 vs FP64 spectra at 256^3, nu = 0.0025 and at 64^3 nu = 0.01
     prec = {}
-    for n, nu, steps, every in ((256, 0.0025, 400, 100), (64, 0.01, 800, 100)):
+    for n, nu, steps, every in (((256, 0.0025, 400, 100), (64, 0.01, 800, 100)) if "precision" in want else ()):
         for method in ("mrt", "dugks"):
             print("bench: precision %s %d" % (method, n), file=sys.stderr, flush=True)
             u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
@@ -170,7 +210,10 @@ def extras(torch, dhit):
                                              "outputs": [{kk: (round(vv, 8) if isinstance(vv, float) else vv)
                                                           for kk, vv in r.items()} for r in rep]}
             torch.cuda.empty_cache()
-    out["precision"] = prec
+    if "precision" in want:
+        out["precision"] = prec
+    if "stability" not in want:
+        return out
     # stability (Sec. IV.E): largest stable Re_lambda at 128^3, FP64, over 6000 time units
     from paper_1601_03815_amd import stability
     print("bench: stability", file=sys.stderr, flush=True)
@@ -193,8 +236,9 @@ def main():
     ap.add_argument("--nu", type=float, default=0.0025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--extras", action="store_true",
-                    help="also run the ensemble, serving and precision configurations (minutes)")
+    ap.add_argument("--extras", nargs="?", const="all", default=None,
+                    help="also run extra configurations (minutes): 'all' or a comma list of "
+                         "ensemble, serving, precision, stability, mesh")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -320,7 +364,7 @@ def main():
                               "dugks": round(r["mlups_dugks"], 1),
                               "speedup_vs_fp64": round(r["mlups"] / fp64["mlups"], 3)}
     if args.extras:
-        line["extras"] = extras(torch, dhit)
+        line["extras"] = extras(torch, dhit, args.extras)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, nu, u)
