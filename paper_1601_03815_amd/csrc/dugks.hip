@@ -45,6 +45,15 @@ __global__ __launch_bounds__(kBlock) void dugks_transform_kernel(const Real *__r
   static_for<kQ>([&](auto q) { fbp[(int64_t)q * stride + cell] = feq[q] + a * (f[q] - feq[q]); });
 }
 
+// Block numbering for the face kernels: blocks are dealt to the eight XCDs
+// in turn (block b runs on XCD b mod 8), so block b takes the row range
+// that puts consecutive rows, and so a cell's y and z neighbour rows, on
+// the same XCD and its L2.  A bijection of [0, nblocks) for any nblocks.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int xcd = b & 7, per = nblocks >> 3, extra = nblocks & 7;
+  return xcd * per + (xcd < extra ? xcd : extra) + (b >> 3);
+}
+
 // Offsets of the 3x3x3 neighbourhood of a cell: off(dx,dy,dz) = X[dx] + Y[dy] + Z[dz].
 struct Nbr {
   int X[3], Y[3], Z[3];  // index 0 = -1, 1 = 0, 2 = +1
@@ -104,7 +113,8 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
                                                             Real *__restrict__ out, StepParams p, int ncell,
                                                             double *__restrict__ partials) {
   const int n = p.n;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  const int block = xcd_block(blockIdx.x, gridDim.x);
+  const int cell = block * kBlock + threadIdx.x;
   double v[kNumSums] = {0, 0, 0, 0, 0};
   if (cell < ncell) {
     const int x = cell % n;
@@ -136,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
     });
     sums_of_populations<Real>(o, p.inv_rho0, v);
   }
-  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+  write_block_partials(v, partials, gridDim.x, block);
 }
 
 // Face at side S of the cell along axis D on a stretched mesh; adds
@@ -202,7 +212,8 @@ __global__ __launch_bounds__(kBlock) void dugks_mesh_face_kernel(const Real *__r
                                                                  const double *__restrict__ mesh,
                                                                  double *__restrict__ partials) {
   const int n = p.n;
-  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  const int block = xcd_block(blockIdx.x, gridDim.x);
+  const int cell = block * kBlock + threadIdx.x;
   double v[kNumSums] = {0, 0, 0, 0, 0};
   if (cell < ncell) {
     const int x = cell % n;
@@ -238,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void dugks_mesh_face_kernel(const Real *__r
                        mesh[(2 * kMeshTables + kMeshWidth) * n + z];
     static_for<kNumSums>([&](auto i) { v[i] = vol * c[i]; });
   }
-  write_block_partials(v, partials, gridDim.x, blockIdx.x);
+  write_block_partials(v, partials, gridDim.x, block);
 }
 
 template <typename Real>
