@@ -237,3 +237,25 @@ def test_mesh_validation_and_reset():
         b.step(1)
         c.step(1)
         assert np.array_equal(b.get_populations(), c.get_populations())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_mesh_conservation_256(precision, tol):
+    """256^3 DHIT field on the stretched mesh (the benchmark's grid), 20
+    steps at CFL 0.9: the volume-weighted mass and momentum of the step
+    history stay at their initial values (the oracle's conservation pin, at
+    a size it cannot run); the weighted kinetic energy decays."""
+    import paper_1601_03815_amd as dhit
+    n = 256
+    W = synth.stretched_widths(n, AMP)
+    dt = 0.9 * W.min() / np.sqrt(2.0)
+    with dhit.Box(n, "dugks", precision, 0.01, dt=dt) as b:
+        b.set_mesh(W)
+        b.init_velocity_field(synth.dhit_field(n, seed=1, k0=4, u_rms=0.05))
+        _d, _j, s0 = b.moments(want_fields=False)
+        b.step(20)
+        h = b.sums_history(20)
+    scale = 0.05 * float(n) ** 3  # |u| ~ u' summed over the volume
+    assert np.abs(h[:, 0:4] - s0[0:4]).max() <= tol * scale, np.abs(h[:, 0:4] - s0[0:4]).max()
+    assert np.all(np.diff(h[:, 4]) < 0)

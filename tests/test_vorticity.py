@@ -56,3 +56,50 @@ def test_vorticity_parity(method, precision, n):
         _d, j, _s = b.moments()
     ref = oracle.vorticity(j)  # u = j / rho0 with rho0 = 1
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+def test_vorticity_parity_128():
+    """128^3 MRT box after 3 steps: every element within 1e-12 of the oracle."""
+    import oracle
+    import paper_1601_03815_amd as dhit
+    n = 128
+    with dhit.Box(n, "mrt", "fp64", 0.005) as b:
+        b.init_velocity_field(synth.dhit_field(n, seed=1, k0=4, u_rms=0.05))
+        b.step(3)
+        got = b.vorticity()
+        _d, j, _s = b.moments()
+    ref = oracle.vorticity(j)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["mrt", "dugks"])
+def test_vorticity_enstrophy_256(method):
+    """256^3, the benchmark's field and viscosity, after 4 steps: the
+    library's curl and its spectrum (two separate code paths: inverse
+    transforms of i kappa x u_hat against kappa^2-weighted shell sums) obey
+    <|omega|^2> + <(div u)^2> = eps / nu (|kappa|^2 |u_hat|^2 = |kappa x u_hat|^2
+    + |kappa . u_hat|^2 mode by mode; the flow is weakly compressible, so
+    the divergence term, 2e-3 of eps/nu here, is needed), to 1e-10."""
+    import paper_1601_03815_amd as dhit
+    n, nu = 256, 0.0025
+    with dhit.Box(n, method, "fp64", nu) as b:
+        b.init_velocity_field(synth.dhit_field(n, seed=1, k0=4, u_rms=0.05))
+        b.step(4)
+        w = b.vorticity()
+        _E, st = b.energy_spectrum()
+        _d, j, _s = b.moments()
+    ens = float(np.mean(np.sum(w * w, axis=0)))
+    del w
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    k1 = np.where(np.abs(k1) == n // 2, 0.0, k1) * (2 * np.pi / n)
+    div_h = np.zeros((n, n, n), dtype=np.complex128)
+    for a in range(3):
+        shape = [1, 1, 1]
+        shape[2 - a] = n   # axis 2 is x, 1 is y, 0 is z
+        div_h += 1j * k1.reshape(shape) * np.fft.fftn(j[a])
+    div2 = float(np.mean(np.fft.ifftn(div_h).real ** 2))
+    ref = st["eps"] / nu
+    assert abs(ens + div2 - ref) <= 1e-10 * ref, (ens, div2, ref)
+    assert div2 < 0.01 * ref
