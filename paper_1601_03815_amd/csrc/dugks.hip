@@ -61,8 +61,9 @@ struct Nbr {
 };
 
 // Face f (all fluxing populations) of the face at side s (+1 / -1) of the
-// cell along axis D; accumulates s * xi_D * f_face into acc.
-template <int D, int S, typename Real>
+// cell along axis D; accumulates s * xi_D * f_face into acc.  Off32 as in
+// face_accumulate_mesh.
+template <int D, int S, bool Off32, typename Real>
 __device__ __forceinline__ void face_accumulate(const Real *__restrict__ fbp, int cell, const Nbr &nb,
                                                 const StepParams &p, Real (&acc)[kQ]) {
   const int64_t stride = p.stride;
@@ -82,18 +83,27 @@ __device__ __forceinline__ void face_accumulate(const Real *__restrict__ fbp, in
   Real fbar[kQ];
   static_for<kQ>([&](auto q) {
     const Real *fq = fbp + (int64_t)q * stride + cell;
-    const Real fl = fq[off(l, 0, 0)], fr = fq[off(r, 0, 0)];
+    const uint32_t qoff = (uint32_t)q * (uint32_t)stride + (uint32_t)cell;
+    auto ld = [&](int o) {
+      if constexpr (Off32)
+        return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(fbp) +
+                                               (uint32_t)(qoff + (uint32_t)o) * (uint32_t)sizeof(Real));
+      else
+        return fq[o];
+    };
+    const Real fl = ld(off(l, 0, 0)), fr = ld(off(r, 0, 0));
     const Real sd = fr - fl;
     Real tang = Real(0);
     if constexpr (cdir(q, T1) != 0) {
-      const Real st = Real(0.25) * ((fq[off(l, 1, 0)] - fq[off(l, -1, 0)]) + (fq[off(r, 1, 0)] - fq[off(r, -1, 0)]));
+      const Real st = Real(0.25) * ((ld(off(l, 1, 0)) - ld(off(l, -1, 0))) + (ld(off(r, 1, 0)) - ld(off(r, -1, 0))));
       tang += Real(cdir(q, T1)) * st;
     }
     if constexpr (cdir(q, T2) != 0) {
-      const Real st = Real(0.25) * ((fq[off(l, 0, 1)] - fq[off(l, 0, -1)]) + (fq[off(r, 0, 1)] - fq[off(r, 0, -1)]));
+      const Real st = Real(0.25) * ((ld(off(l, 0, 1)) - ld(off(l, 0, -1))) + (ld(off(r, 0, 1)) - ld(off(r, 0, -1))));
       tang += Real(cdir(q, T2)) * st;
     }
     fbar[q] = (fl + Real(0.5) * sd) - h * (Real(cdir(q, D)) * sd + tang);
+    if constexpr (std::is_same<Real, double>::value && q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
   });
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(fbar, drho, jx, jy, jz);
@@ -108,7 +118,7 @@ __device__ __forceinline__ void face_accumulate(const Real *__restrict__ fbp, in
   });
 }
 
-template <typename Real>
+template <typename Real, bool Off32>
 __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restrict__ ft, const Real *__restrict__ fbp,
                                                             Real *__restrict__ out, StepParams p, int ncell,
                                                             double *__restrict__ partials) {
@@ -128,12 +138,17 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
     nb.Z[0] = oz.dn; nb.Z[1] = 0; nb.Z[2] = oz.up;
     Real acc[kQ];
     static_for<kQ>([&](auto q) { acc[q] = Real(0); });
-    face_accumulate<0, 1, Real>(fbp, cell, nb, p, acc);
-    face_accumulate<0, -1, Real>(fbp, cell, nb, p, acc);
-    face_accumulate<1, 1, Real>(fbp, cell, nb, p, acc);
-    face_accumulate<1, -1, Real>(fbp, cell, nb, p, acc);
-    face_accumulate<2, 1, Real>(fbp, cell, nb, p, acc);
-    face_accumulate<2, -1, Real>(fbp, cell, nb, p, acc);
+    face_accumulate<0, 1, Off32, Real>(fbp, cell, nb, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate<0, -1, Off32, Real>(fbp, cell, nb, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate<1, 1, Off32, Real>(fbp, cell, nb, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate<1, -1, Off32, Real>(fbp, cell, nb, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate<2, 1, Off32, Real>(fbp, cell, nb, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate<2, -1, Off32, Real>(fbp, cell, nb, p, acc);
     const int64_t stride = p.stride;
     const Real dt = Real(p.dt);
     Real o[kQ];
@@ -151,7 +166,9 @@ __global__ __launch_bounds__(kBlock) void dugks_face_kernel(const Real *__restri
 
 // Face at side S of the cell along axis D on a stretched mesh; adds
 // S xi_D f_face / w_D(cell) to acc.  pos = the cell's (x, y, z).
-template <int D, int S, typename Real>
+// Off32: address the field with 32-bit byte offsets from its base (valid
+// when the whole field is below 4 GB; fewer live address registers).
+template <int D, int S, bool Off32, typename Real>
 __device__ __forceinline__ void face_accumulate_mesh(const Real *__restrict__ fbp, int cell, const Nbr &nb,
                                                      const int (&pos)[3], const double *__restrict__ mesh,
                                                      const StepParams &p, Real (&acc)[kQ]) {
@@ -177,18 +194,31 @@ __device__ __forceinline__ void face_accumulate_mesh(const Real *__restrict__ fb
   Real fbar[kQ];
   static_for<kQ>([&](auto q) {
     const Real *fq = fbp + (int64_t)q * stride + cell;
-    const Real fl = fq[off(l, 0, 0)], fr = fq[off(r, 0, 0)];
+    const uint32_t qoff = (uint32_t)q * (uint32_t)stride + (uint32_t)cell;
+    auto ld = [&](int o) {
+      if constexpr (Off32)  // element q*stride + cell + o, as a byte offset (wraps back into range for o < 0)
+        return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(fbp) +
+                                               (uint32_t)(qoff + (uint32_t)o) * (uint32_t)sizeof(Real));
+      else
+        return fq[o];
+    };
+    const Real fl = ld(off(l, 0, 0)), fr = ld(off(r, 0, 0));
     const Real sd = fr - fl;
     Real tang = Real(0);
     if constexpr (cdir(q, T1) != 0) {
-      const Real gl = fq[off(l, 1, 0)] - fq[off(l, -1, 0)], gr = fq[off(r, 1, 0)] - fq[off(r, -1, 0)];
+      const Real gl = ld(off(l, 1, 0)) - ld(off(l, -1, 0)), gr = ld(off(r, 1, 0)) - ld(off(r, -1, 0));
       tang += Real(cdir(q, T1)) * (inv_span1 * (gl + lam * (gr - gl)));
     }
     if constexpr (cdir(q, T2) != 0) {
-      const Real gl = fq[off(l, 0, 1)] - fq[off(l, 0, -1)], gr = fq[off(r, 0, 1)] - fq[off(r, 0, -1)];
+      const Real gl = ld(off(l, 0, 1)) - ld(off(l, 0, -1)), gr = ld(off(r, 0, 1)) - ld(off(r, 0, -1));
       tang += Real(cdir(q, T2)) * (inv_span2 * (gl + lam * (gr - gl)));
     }
     fbar[q] = (fl + lam * sd) - h * (Real(cdir(q, D)) * (sd * inv_gap) + tang);
+    // FP64: keep the scheduler from hoisting the loads of the whole face: with
+    // them in flight at once the kernel needs more than 256 registers (one
+    // wave per SIMD); in groups of four populations it runs two.  FP32 fits
+    // two waves without this and is faster with the full face in flight.
+    if constexpr (std::is_same<Real, double>::value && q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
   });
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(fbar, drho, jx, jy, jz);
@@ -205,7 +235,7 @@ __device__ __forceinline__ void face_accumulate_mesh(const Real *__restrict__ fb
 
 // Face kernel of the stretched mesh; the five sums are weighted by the
 // cell volumes w_x w_y w_z.
-template <typename Real>
+template <typename Real, bool Off32>
 __global__ __launch_bounds__(kBlock) void dugks_mesh_face_kernel(const Real *__restrict__ ft,
                                                                  const Real *__restrict__ fbp, Real *__restrict__ out,
                                                                  StepParams p, int ncell,
@@ -228,12 +258,18 @@ __global__ __launch_bounds__(kBlock) void dugks_mesh_face_kernel(const Real *__r
     nb.Z[0] = oz.dn; nb.Z[1] = 0; nb.Z[2] = oz.up;
     Real acc[kQ];
     static_for<kQ>([&](auto q) { acc[q] = Real(0); });
-    face_accumulate_mesh<0, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
-    face_accumulate_mesh<0, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
-    face_accumulate_mesh<1, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
-    face_accumulate_mesh<1, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
-    face_accumulate_mesh<2, 1, Real>(fbp, cell, nb, pos, mesh, p, acc);
-    face_accumulate_mesh<2, -1, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    // FP64: one face at a time (see the register note in face_accumulate_mesh)
+    face_accumulate_mesh<0, 1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate_mesh<0, -1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate_mesh<1, 1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate_mesh<1, -1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate_mesh<2, 1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
+    if constexpr (std::is_same<Real, double>::value) __builtin_amdgcn_sched_barrier(0);
+    face_accumulate_mesh<2, -1, Off32, Real>(fbp, cell, nb, pos, mesh, p, acc);
     const int64_t stride = p.stride;
     const Real dt = Real(p.dt);
     Real o[kQ];
@@ -267,8 +303,14 @@ static void dugks_mesh_two_pass(dhit_box &b, const void *src, void *dst, double 
   }
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FACE);
-    hipLaunchKernelGGL((dugks_mesh_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
-                       (int)b.ncell, b.mesh, b.partials);
+    // 32-bit byte offsets when the whole field (19 padded arrays) is below 4 GB
+    const bool off32 = (uint64_t)kQ * (uint64_t)b.stride * sizeof(Real) < (uint64_t(1) << 32);
+    if (off32)
+      hipLaunchKernelGGL((dugks_mesh_face_kernel<Real, true>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d,
+                         b.sp, (int)b.ncell, b.mesh, b.partials);
+    else
+      hipLaunchKernelGGL((dugks_mesh_face_kernel<Real, false>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d,
+                         b.sp, (int)b.ncell, b.mesh, b.partials);
     DHIT_HIP(hipGetLastError());
     t.done();
   }
@@ -290,8 +332,13 @@ static void dugks_two_pass(dhit_box &b, const void *src, void *dst, double *sums
   }
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FACE);
-    hipLaunchKernelGGL((dugks_face_kernel<Real>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
-                       (int)b.ncell, b.partials);
+    const bool off32 = (uint64_t)kQ * (uint64_t)b.stride * sizeof(Real) < (uint64_t(1) << 32);
+    if (off32)
+      hipLaunchKernelGGL((dugks_face_kernel<Real, true>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
+                         (int)b.ncell, b.partials);
+    else
+      hipLaunchKernelGGL((dugks_face_kernel<Real, false>), dim3(blocks), dim3(kBlock), 0, b.stream, s, bp, d, b.sp,
+                         (int)b.ncell, b.partials);
     DHIT_HIP(hipGetLastError());
     t.done();
   }
