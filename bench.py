@@ -243,8 +243,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the per-step update of one box is not "
-              "sharded (see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the per-step update of a box is not sharded across "
+              "GPUs (a z-slab split with halo exchange would be the way). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
