@@ -148,8 +148,9 @@ int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
  * DHIT_EINVAL for a width that is not finite and > 0, or for
  * sqrt(2) dt > min width (CFL above 1; the paper takes
  * dt = CFL dx_min / sqrt(2)).  Boxes with a stretched mesh cannot be batched
- * (a batch built before the call keeps stepping them on unit cells), and
- * energy_spectrum and vorticity reject them (DHIT_EMETHOD). */
+ * (create_batch and step_batch reject them, and batch_step of a batch built
+ * before the call returns DHIT_EINVAL), and energy_spectrum and vorticity
+ * reject them (DHIT_EMETHOD). */
 int32_t set_mesh(dhit_box *b, const double *widths);
 
 /* Consistent initial state of an LBE box for a prescribed velocity field

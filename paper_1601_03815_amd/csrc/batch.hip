@@ -342,6 +342,8 @@ int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune_flag, dhit
 int32_t batch_step(dhit_batch *bt, int32_t nsteps) {
   return guarded_batch([&]() -> int32_t {
     if (!bt) throw dhit::Error(DHIT_EINVAL, "null batch");
+    for (const dhit_box *b : bt->boxes)  // set_mesh after the batch was built
+      if (b->mesh) throw dhit::Error(DHIT_EINVAL, "a box of the batch has a stretched mesh");
     run_steps(*bt, nsteps, true);
     return DHIT_OK;
   });

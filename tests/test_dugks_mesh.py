@@ -227,6 +227,16 @@ def test_mesh_validation_and_reset():
         assert e.value.code == -4
         with pytest.raises(dhit.DhitError):
             dhit.step_batch([b.handle, c.handle], 1)
+        b.set_mesh(None)
+        bt = dhit.create_batch([b.handle, c.handle], autotune=False)
+        try:
+            b.set_mesh(W)   # after the batch was built
+            with pytest.raises(dhit.DhitError) as e:
+                dhit.batch_step(bt, 1)
+            assert e.value.code == -1
+        finally:
+            dhit.destroy_batch(bt)
+        b.set_mesh(W)
         b.set_mesh(np.ones((3, n)))
         b.set_populations(f0)
         b.step(1)

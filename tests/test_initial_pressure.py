@@ -161,6 +161,11 @@ def test_init_consistent_edge_cases():
         with pytest.raises(dhit.DhitError) as e:
             c.init_consistent(u, d0, 3)
         assert e.value.code == -4
+    bad = u.copy()
+    bad[1, 3, 4, 5] = np.nan
+    with dhit.Box(n, "bgk", "fp64", 0.01) as d:
+        with pytest.raises(dhit.NonFiniteError):
+            d.init_consistent(bad, d0, 2)
 
 
 @pytest.mark.gpu
