@@ -103,7 +103,7 @@ __device__ __forceinline__ void face_accumulate(const Real *__restrict__ fbp, in
       tang += Real(cdir(q, T2)) * st;
     }
     fbar[q] = (fl + Real(0.5) * sd) - h * (Real(cdir(q, D)) * sd + tang);
-    if constexpr (std::is_same<Real, double>::value && q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (std::is_same<Real, double>::value && q % 2 == 1) __builtin_amdgcn_sched_barrier(0);
   });
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(fbar, drho, jx, jy, jz);
@@ -216,9 +216,9 @@ __device__ __forceinline__ void face_accumulate_mesh(const Real *__restrict__ fb
     fbar[q] = (fl + lam * sd) - h * (Real(cdir(q, D)) * (sd * inv_gap) + tang);
     // FP64: keep the scheduler from hoisting the loads of the whole face: with
     // them in flight at once the kernel needs more than 256 registers (one
-    // wave per SIMD); in groups of four populations it runs two.  FP32 fits
+    // wave per SIMD); in pairs of populations it runs two.  FP32 fits
     // two waves without this and is faster with the full face in flight.
-    if constexpr (std::is_same<Real, double>::value && q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (std::is_same<Real, double>::value && q % 2 == 1) __builtin_amdgcn_sched_barrier(0);
   });
   Real drho, jx, jy, jz, feq[kQ];
   cell_moments<Real>(fbar, drho, jx, jy, jz);
