@@ -153,8 +153,11 @@ def extras(torch, dhit, sections="all"):
     a comma list of their names."""
     import synth
     from paper_1601_03815_amd import ensemble, precision, serve
-    want = set(("ensemble", "serving", "precision", "stability", "mesh") if sections == "all"
-               else sections.split(","))
+    known = ("ensemble", "serving", "precision", "stability", "mesh")
+    want = set(known if sections == "all" else sections.split(","))
+    if want - set(known):
+        raise SystemExit("bench.py: unknown --extras section(s) %s; known: %s"
+                         % (",".join(sorted(want - set(known))), ",".join(known)))
     out = {}
     if "mesh" in want:
         out["mesh"] = mesh_costs(torch, dhit)
