@@ -18,7 +18,10 @@ t' = t eps0 / K0 (t0 = K0/eps0 of the initial field), velocity magnitude
 in lattice units.
 
 `DhitStatistics.record` steps a box and collects these as time series;
-`normalized_slices` gives the two magnitude fields on a plane z = const.
+`normalized_slices` gives the two magnitude fields on a plane z = const;
+`to_spectral_units` converts a record to the units of the paper's
+pseudo-spectral runs (box 2 pi, velocities divided by the velocity scale V_s,
+Sec. IV.A).
 """
 import math
 
@@ -87,3 +90,37 @@ def normalized_slices(box, u0_rms, z=None):
     u = j[:, z] / box.params.rho0
     w = box.vorticity()[:, z]
     return np.sqrt(np.sum(u * u, axis=0)) / u0_rms, np.sqrt(np.sum(w * w, axis=0)) * n / u0_rms
+
+
+def lattice_viscosity(nu_spectral, v_s, n):
+    """Viscosity in lattice units (cell size 1, box n) of a flow whose
+    spectral-unit viscosity is nu_spectral (box 2 pi) at velocity scale v_s:
+    lengths scale by n / (2 pi), velocities by v_s, so nu = x^2/t scales by
+    v_s n / (2 pi)."""
+    return nu_spectral * v_s * n / (2.0 * math.pi)
+
+
+def to_spectral_units(rec, v_s, n):
+    """A record of `statistics` / `DhitStatistics` (lattice units, box n) in
+    the paper's spectral units (Sec. IV.A): with ls = 2 pi / n the spectral
+    length of one cell, u -> u / v_s, x -> x ls, t -> t ls v_s; so
+    K -> K / v_s^2, eps and D(k) -> / (ls v_s^3), lambda and eta -> x ls,
+    the shell energies E[k] -> / v_s^2 (integer shells are the same in both
+    systems), nu -> nu ls / v_s.  Re_lambda, kmax eta, S, F and the
+    eddy-turnover time t' are dimensionless and kept."""
+    ls = 2.0 * math.pi / n
+    out = dict(rec)
+    out["K"] = rec["K"] / v_s ** 2
+    out["u_rms"] = rec["u_rms"] / v_s
+    out["eps"] = rec["eps"] / (ls * v_s ** 3)
+    out["lambda"] = rec["lambda"] * ls
+    out["eta"] = rec["eta"] * ls
+    if "D" in rec:
+        out["D"] = np.asarray(rec["D"]) / (ls * v_s ** 3)
+    if "E" in rec:
+        out["E"] = np.asarray(rec["E"]) / v_s ** 2
+    if "t" in rec:
+        out["t"] = rec["t"] * ls * v_s
+    if "nu" in rec:
+        out["nu"] = rec["nu"] * ls / v_s
+    return out

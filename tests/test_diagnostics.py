@@ -105,3 +105,55 @@ def test_normalized_slices_taylor_green():
     ref_u = np.sqrt(np.sin(X) ** 2 * np.cos(Y) ** 2 + np.cos(X) ** 2 * np.sin(Y) ** 2)
     assert np.abs(su - ref_u).max() < 1e-13
     assert np.abs(sw - 4 * np.pi * np.abs(np.sin(X) * np.sin(Y))).max() < 1e-11
+
+
+def _table1():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_parameters.json")))
+
+
+def test_unit_conversion_reproduces_table1():
+    """The paper's lattice runs are its spectral runs at velocity scale
+    V_s = 0.0408 (Sec. IV.A, Table I): K0 and u'0 scale by V_s^2 and V_s
+    (1.5383e-3 and 0.0320 as printed, to their 4-5 digits) and the viscosity
+    by V_s n / (2 pi) (1.2395e-2 at 128^3 and 2.4790e-2 at 256^3 as printed;
+    the conversion gives 1.2412e-2 and 2.4824e-2, 0.14% above: the printed
+    pair corresponds to V_s = 0.04074, within the rounding of 0.0408)."""
+    from paper_1601_03815_amd.diagnostics import lattice_viscosity
+    t = _table1()
+    vs, ps = t["v_s"], t["ps"]
+    for n in ("128", "256"):
+        lat = t["lattice"][n]
+        assert vs ** 2 * ps["K0"] == pytest.approx(lat["K0"], rel=2e-4)
+        assert vs * ps["u0"] == pytest.approx(lat["u0"], rel=1e-3)
+        assert lattice_viscosity(ps["nu"], vs, int(n)) == pytest.approx(lat["nu"], rel=2e-3)
+    assert t["lattice"]["256"]["nu"] == pytest.approx(2 * t["lattice"]["128"]["nu"], rel=1e-12)
+
+
+def test_to_spectral_units_is_consistent():
+    """The converted record satisfies the Sec. III relations in the new
+    units: u' = sqrt(2K/3), lambda = sqrt(15 nu / eps) u', Re_lambda =
+    u' lambda / nu, eta = (nu^3/eps)^(1/4), sum D = eps for on-shell
+    modes; the dimensionless quantities are unchanged."""
+    from paper_1601_03815_amd.diagnostics import statistics, to_spectral_units
+    n, nu, vs = 64, 0.004, 0.0408
+    E = np.zeros(n // 2 + 1)
+    E[1:9] = np.random.default_rng(3).uniform(0.0, 1e-4, 8)
+    kappa = 2 * math.pi * np.arange(len(E)) / n
+    st = {"K": E.sum(), "eps": 2 * nu * np.sum(kappa ** 2 * E), "S": -0.4, "F": 4.0}
+    rec = statistics(E, st, nu, n)
+    rec.update(t=250.0, E=E, nu=nu, t_prime=1.7)
+    sp = to_spectral_units(rec, vs, n)
+    assert sp["u_rms"] == pytest.approx(math.sqrt(2 * sp["K"] / 3), rel=1e-13)
+    assert sp["lambda"] == pytest.approx(math.sqrt(15 * sp["nu"] / sp["eps"]) * sp["u_rms"], rel=1e-13)
+    assert sp["u_rms"] * sp["lambda"] / sp["nu"] == pytest.approx(rec["re_lambda"], rel=1e-13)
+    assert sp["eta"] == pytest.approx((sp["nu"] ** 3 / sp["eps"]) ** 0.25, rel=1e-13)
+    assert sp["D"].sum() == pytest.approx(sp["eps"], rel=1e-13)
+    assert sp["E"].sum() == pytest.approx(sp["K"], rel=1e-13)
+    ks = np.arange(len(E))  # spectral wavenumbers are the integer shells
+    assert 2 * sp["nu"] * np.sum(ks ** 2 * sp["E"]) == pytest.approx(sp["eps"], rel=1e-13)
+    for key in ("re_lambda", "kmax_eta", "S", "F", "t_prime"):
+        assert sp[key] == rec[key]
+    # time in units of the large-eddy time L/u is the same in both systems
+    assert sp["t"] * sp["u_rms"] / (2 * math.pi) == pytest.approx(rec["t"] * rec["u_rms"] / n, rel=1e-13)
