@@ -124,7 +124,7 @@ def _weighted_sums(f, W):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n", [5, 12, 17, 32])
+@pytest.mark.parametrize("n", [4, 5, 12, 17, 32])
 def test_mesh_step_parity_fp64(n):
     """Two steps from a random state on a stretched mesh, element by
     element within 1e-12 of the oracle, with the volume-weighted sums of the

@@ -100,7 +100,7 @@ def test_consistent_pressure_removes_the_startup_transient(method):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("method", ["bgk", "mrt"])
-@pytest.mark.parametrize("n,iters", [(17, 7), (32, 20)])
+@pytest.mark.parametrize("n,iters", [(4, 3), (17, 7), (32, 20)])
 def test_init_consistent_parity_fp64(method, n, iters):
     """The library's iteration against the oracle's, element by element
     (LBE boxes store post-collision populations: compared with the oracle's

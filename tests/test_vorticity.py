@@ -103,3 +103,16 @@ def test_vorticity_enstrophy_256(method):
     ref = st["eps"] / nu
     assert abs(ens + div2 - ref) <= 1e-10 * ref, (ens, div2, ref)
     assert div2 < 0.01 * ref
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [4, 9])
+def test_vorticity_of_uniform_flow_is_zero(n):
+    """Degenerate case: a uniform flow (only the k = 0 mode) has no
+    vorticity; smallest grids, odd and even."""
+    import paper_1601_03815_amd as dhit
+    with dhit.Box(n, "bgk", "fp64", 0.01) as b:
+        b.init_velocity_field(synth.uniform_flow(n, 0.03, -0.02, 0.01))
+        w = b.vorticity()
+    assert w.shape == (3, n, n, n)
+    assert np.abs(w).max() < 1e-17
