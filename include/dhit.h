@@ -153,6 +153,20 @@ int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
  * reject them (DHIT_EMETHOD). */
 int32_t set_mesh(dhit_box *b, const double *widths);
 
+/* Density fluctuation that belongs to a velocity field (Sec. IV.A: the
+ * initial pressure comes from the Poisson equation in spectral space, and
+ * the kinetic schemes take it through the equation of state): the
+ * incompressible pressure p with lap p = -rho0 d_i d_j (u_i u_j), computed
+ * with the box's hipFFT work space on the integer wavevectors of the n^3
+ * grid, p_hat = -rho0 sum_ij k_i k_j (u_i u_j)_hat / |k|^2 (zero mean; the
+ * Nyquist component of each derivative factor dropped, as for S and F),
+ * and drho = p / c_s^2 = 3 p.  u: host [3][n^3], drho: host [n^3], both
+ * idx = (z*n + y)*n + x; the box's state is not touched (only its n, rho0,
+ * stream and spectrum work space are used).  The natural drho argument of
+ * init_velocity_field and init_consistent.  Synchronous; allocates an
+ * upload buffer for the call. */
+int32_t initial_pressure(dhit_box *b, const double *u, double *drho);
+
 /* Consistent initial state of an LBE box for a prescribed velocity field
  * (Sec. IV.A: the kinetic schemes start from the density fluctuation and
  * the non-equilibrium part that belong to the initial velocity, found by

@@ -315,6 +315,33 @@ def init_mrt_equilibrium(u, drho=None, rho0=1.0, w_eps=0.0, w_epsj=-475.0 / 63.0
     return f
 
 
+
+def initial_pressure(u, rho0=1.0):
+    """Density fluctuation consistent with a velocity field (Sec. IV.A: the
+    initial pressure comes from the Poisson equation in spectral space; the
+    kinetic schemes take it through the equation of state).  The
+    incompressible pressure solves lap p = -rho0 d_i d_j (u_i u_j): in
+    Fourier space on the integer wavevectors of the periodic grid,
+    p_hat = -rho0 sum_ij k_i k_j (u_i u_j)_hat / |k|^2 (zero mean), with the
+    Nyquist component of each derivative factor k_i dropped as for S and F;
+    drho = p / c_s^2 = 3 p (RT = 1/3).  Returns drho[n, n, n]."""
+    u = _f64(u)
+    n = u.shape[1]
+    k = wavenumbers(n)
+    kd = np.where(np.abs(k) == n // 2, 0.0, k) if n % 2 == 0 else k
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    dz, dy, dx = np.meshgrid(kd, kd, kd, indexing="ij")
+    kv = (dx, dy, dz)  # component a of u is u[a], a = 0 (x), 1 (y), 2 (z)
+    k2 = kx * kx + ky * ky + kz * kz
+    k2[0, 0, 0] = 1.0
+    rhs = np.zeros((n, n, n), dtype=np.complex128)
+    for a in range(3):
+        for b in range(3):
+            rhs += kv[a] * kv[b] * np.fft.fftn(u[a] * u[b])
+    p_hat = -rho0 * rhs / k2
+    p_hat[0, 0, 0] = 0.0
+    return 3.0 * np.real(np.fft.ifftn(p_hat))
+
 # ----------------------------------------------------------------------------
 # Consistent initial state, Sec. IV.A
 # ----------------------------------------------------------------------------

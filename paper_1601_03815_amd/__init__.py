@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     DUGKS, FP32, FP64, LBE_BGK, LBE_MRT, METHODS, PRECISIONS, VARIANT_DEFAULT, VARIANT_TWO_PASS,
     DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, set_mesh, last_error,
-    moments, vorticity, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
+    moments, vorticity, initial_pressure, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
     create_batch, batch_step, batch_info, destroy_batch,
 )
@@ -116,6 +116,11 @@ class Box:
         if kmax is None:
             kmax = self.n // 2
         return energy_spectrum(self.handle, kmax)
+
+    def initial_pressure(self, u):
+        """drho = 3 p consistent with velocity field u (3, n, n, n), on the GPU
+        (the box's state is not touched)."""
+        return initial_pressure(self.handle, self.n, u)
 
     def vorticity(self):
         """Vorticity of the current velocity field, (3, n, n, n) doubles in

@@ -87,6 +87,7 @@ def _load():
         "sums_history": ([box, dp, i32], i32),
         "energy_spectrum": ([box, dp, i32, dp], i32),
         "vorticity": ([box, dp], i32),
+        "initial_pressure": ([box, dp, dp], i32),
         "get_populations": ([box, dp], i32),
         "set_populations": ([box, dp], i32),
         "steps_taken": ([box], i64),
@@ -225,6 +226,14 @@ def energy_spectrum(h, kmax):
     return E, dict(K=st[0], eps=st[1], S=st[2], F=st[3])
 
 
+def initial_pressure(h, n, u):
+    """drho = 3 p of the incompressible pressure of velocity field u (3, n, n, n)."""
+    u = _f64_in(u, (3, n, n, n))
+    d = _f64_out((n, n, n))
+    _check(_lib.initial_pressure(h, _ptr(u), _ptr(d)))
+    return d
+
+
 def vorticity(h, n):
     """omega = curl(j/rho0) as (3, n, n, n) doubles."""
     w = _f64_out((3, n, n, n))
@@ -309,7 +318,7 @@ def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
 
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
-    "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity",
+    "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",

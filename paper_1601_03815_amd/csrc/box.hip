@@ -475,6 +475,15 @@ int32_t energy_spectrum(dhit_box *b, double *E, int32_t kmax, double *stats) {
   });
 }
 
+int32_t initial_pressure(dhit_box *b, const double *u, double *drho) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!u || !drho) fail(DHIT_EINVAL, "null velocity or output");
+    dhit::pressure_compute(*b, u, drho);
+    return DHIT_OK;
+  });
+}
+
 int32_t vorticity(dhit_box *b, double *omega) {
   return guarded([&]() -> int32_t {
     require_box(b);

@@ -156,6 +156,7 @@ int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_
 void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);
 void spectrum_free(dhit_box &b);
 void vorticity_compute(dhit_box &b, double *omega_host);  // omega = curl(j/rho0), host [3][ncell]
+void pressure_compute(dhit_box &b, const double *u_host, double *drho_host);  // drho = 3 p of a host u
 
 // Event bracket around one kernel launch when timing is enabled:
 //   TimedLaunch t(b, DHIT_K_LBE); hipLaunchKernelGGL(...); t.done();

@@ -113,6 +113,68 @@ __global__ __launch_bounds__(256) void curl_kernel(const hipfftDoubleComplex *__
   out[m] = o;
 }
 
+// Products of velocity components for the pressure source: set 0 gives
+// (u u, v v, w w), set 1 gives (u v, v w, w u), into three fields of out.
+__global__ __launch_bounds__(256) void products_kernel(const double *__restrict__ u, double *__restrict__ out,
+                                                       int64_t ncell, int set) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const double a = u[i], b = u[ncell + i], c = u[2 * ncell + i];
+  if (set == 0) {
+    out[i] = a * a;
+    out[ncell + i] = b * b;
+    out[2 * ncell + i] = c * c;
+  } else {
+    out[i] = a * b;
+    out[ncell + i] = b * c;
+    out[2 * ncell + i] = c * a;
+  }
+}
+
+// acc (half spectrum) (=, set 0) or (+=, set 1) sum over the three
+// transformed products ph of their weights: set 0 k_a^2 for (aa),
+// set 1 2 k_a k_b for (ab) = (xy, yz, zx); k the integer wavevector with the
+// Nyquist component of each derivative factor dropped.
+__global__ __launch_bounds__(256) void pressure_source_kernel(const hipfftDoubleComplex *__restrict__ ph,
+                                                              hipfftDoubleComplex *__restrict__ acc, int n,
+                                                              int64_t nhalf, int set) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nhalf) return;
+  const int nxh = n / 2 + 1;
+  const int64_t r = m / nxh;
+  int k[3] = {(int)(m % nxh), signed_k((int)(r % n), n), signed_k((int)(r / n), n)};
+  for (int i = 0; i < 3; ++i)
+    if ((n % 2 == 0) && (2 * k[i] == n || 2 * k[i] == -n)) k[i] = 0;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double w = set == 0 ? (double)k[c] * k[c] : 2.0 * (double)k[c] * k[(c + 1) % 3];
+    const hipfftDoubleComplex v = ph[(int64_t)c * nhalf + m];
+    re += w * v.x;
+    im += w * v.y;
+  }
+  if (set == 0) {
+    acc[m].x = re;
+    acc[m].y = im;
+  } else {
+    acc[m].x += re;
+    acc[m].y += im;
+  }
+}
+
+// acc <- scale acc / |k|^2 (full integer |k|^2; the k = 0 mode set to 0).
+__global__ __launch_bounds__(256) void inverse_laplacian_kernel(hipfftDoubleComplex *__restrict__ acc, int n,
+                                                                int64_t nhalf, double scale) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nhalf) return;
+  const int nxh = n / 2 + 1;
+  const int64_t r = m / nxh;
+  const int kx = (int)(m % nxh), ky = signed_k((int)(r % n), n), kz = signed_k((int)(r / n), n);
+  const int k2 = kx * kx + ky * ky + kz * kz;
+  const double f = k2 == 0 ? 0.0 : scale / (double)k2;
+  acc[m].x *= f;
+  acc[m].y *= f;
+}
+
 // Sums of d^2, d^3, d^4 of a real field scaled by `scale`.
 __global__ __launch_bounds__(kBlock) void power_sums_kernel(const double *__restrict__ d, int64_t ncell, double scale,
                                                             double *__restrict__ partials) {
@@ -217,6 +279,40 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
   }
   for (int i = 0; i < 15; ++i)
     if (!std::isfinite(ds[i])) throw Error(DHIT_ENONFINITE, "velocity field is not finite");
+}
+
+void pressure_compute(dhit_box &b, const double *u_host, double *drho_host) {
+  ensure_work(b);
+  SpectrumWork &w = *b.spec;
+  const int n = b.n;
+  DHIT_FFT(hipfftSetStream(w.fwd, b.stream));
+  DHIT_FFT(hipfftSetStream(w.inv, b.stream));
+  double *du = nullptr;
+  if (hipMalloc(&du, 3 * b.ncell * sizeof(double)) != hipSuccess)
+    throw Error(DHIT_ENOMEM, "cannot allocate the velocity upload buffer");
+  try {
+    DHIT_HIP(hipMemcpyAsync(du, u_host, 3 * b.ncell * sizeof(double), hipMemcpyHostToDevice, b.stream));
+    const int cb = (int)((b.ncell + 255) / 256), mb = (int)((w.nhalf + 255) / 256);
+    for (int set = 0; set < 2; ++set) {
+      hipLaunchKernelGGL(products_kernel, dim3(cb), dim3(256), 0, b.stream, du, w.u, (int64_t)b.ncell, set);
+      DHIT_HIP(hipGetLastError());
+      DHIT_FFT(hipfftExecD2Z(w.fwd, w.u, w.uh));
+      hipLaunchKernelGGL(pressure_source_kernel, dim3(mb), dim3(256), 0, b.stream, w.uh, w.tmp, n, w.nhalf, set);
+      DHIT_HIP(hipGetLastError());
+    }
+    // p_hat = -rho0 rhs / |k|^2; drho = 3 p; both transforms are unnormalised
+    const double scale = -3.0 * b.p.rho0 / ((double)n * n * n);
+    hipLaunchKernelGGL(inverse_laplacian_kernel, dim3(mb), dim3(256), 0, b.stream, w.tmp, n, w.nhalf, scale);
+    DHIT_HIP(hipGetLastError());
+    DHIT_FFT(hipfftExecZ2D(w.inv, w.tmp, w.u));
+    DHIT_HIP(hipMemcpyAsync(drho_host, w.u, b.ncell * sizeof(double), hipMemcpyDeviceToHost, b.stream));
+    DHIT_HIP(hipStreamSynchronize(b.stream));
+  } catch (...) {
+    (void)hipStreamSynchronize(b.stream);
+    (void)hipFree(du);
+    throw;
+  }
+  (void)hipFree(du);
 }
 
 void vorticity_compute(dhit_box &b, double *omega_host) {

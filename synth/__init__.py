@@ -87,29 +87,6 @@ def dhit_field(n, seed, k0=4.0, u_rms=0.05):
     return np.ascontiguousarray(u * (u_rms / cur))
 
 
-def initial_pressure(u, rho0=1.0):
-    """Density fluctuation consistent with a velocity field (the initial
-    pressure of Sec. IV.A): the incompressible pressure p solves
-    lap p = -rho0 d_i d_j (u_i u_j), solved in Fourier space on the integer
-    wavevectors of the periodic grid (p_hat = -rho0 k_i k_j (u_i u_j)_hat / |k|^2,
-    zero mean), and drho = p / c_s^2 = 3 p (lattice units, RT = 1/3).
-    This is a property of the Navier-Stokes input, shared by both schemes."""
-    u = np.asarray(u, dtype=np.float64)
-    n = u.shape[1]
-    k = np.fft.fftfreq(n, 1.0 / n)
-    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
-    kv = (kx, ky, kz)  # component a of u is u[a] with a = 0 (x), 1 (y), 2 (z)
-    k2 = kx * kx + ky * ky + kz * kz
-    k2[0, 0, 0] = 1.0
-    rhs = np.zeros((n, n, n), dtype=np.complex128)
-    for a in range(3):
-        for b in range(3):
-            rhs += kv[a] * kv[b] * np.fft.fftn(u[a] * u[b])
-    p_hat = -rho0 * rhs / k2
-    p_hat[0, 0, 0] = 0.0
-    return 3.0 * np.real(np.fft.ifftn(p_hat))
-
-
 def random_populations(n, seed, amplitude=1e-2):
     """Independent uniform values in [-amplitude, amplitude] for every
     population of every cell: an arbitrary (non-equilibrium) state."""

@@ -12,18 +12,20 @@ import synth
 
 def test_taylor_green_pressure_closed_form():
     """Taylor-Green vortex: p = rho0 U^2/16 (cos 2x + cos 2y)(cos 2z + 2), drho = 3 p."""
+    import oracle
     n, U = 16, 0.05
     x = synth.grid(n)
     Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
     p = U * U / 16 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)
-    d = synth.initial_pressure(synth.taylor_green(n, U))
+    d = oracle.initial_pressure(synth.taylor_green(n, U))
     assert np.abs(d - 3 * p).max() <= 1e-14 * np.abs(p).max()
 
 
 def test_pressure_of_flows_without_pressure_gradient():
     """A uniform flow and a plane shear wave carry no pressure."""
-    assert np.abs(synth.initial_pressure(synth.uniform_flow(8, 0.03, -0.01, 0.02))).max() == 0.0
-    assert np.abs(synth.initial_pressure(synth.shear_wave(12, 0.02, 2))).max() < 1e-18
+    import oracle
+    assert np.abs(oracle.initial_pressure(synth.uniform_flow(8, 0.03, -0.01, 0.02))).max() == 0.0
+    assert np.abs(oracle.initial_pressure(synth.shear_wave(12, 0.02, 2))).max() < 1e-18
 
 
 @pytest.mark.parametrize("method", ["bgk", "mrt"])
@@ -88,7 +90,8 @@ def test_consistent_pressure_removes_the_startup_transient(method):
     FP64 oracle gives a ratio of 0.22 for both methods at this time."""
     import paper_1601_03815_amd as dhit
     u = synth.dhit_field(32, seed=2, k0=2, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    with dhit.Box(32, method, "fp64", 0.01) as b:
+        d0 = b.initial_pressure(u)
     div = {}
     for label, drho in (("zero", None), ("consistent", d0)):
         with dhit.Box(32, method, "fp64", 0.01) as b:
@@ -110,7 +113,7 @@ def test_init_consistent_parity_fp64(method, n, iters):
     import paper_1601_03815_amd as dhit
     nu = 0.01
     u = synth.dhit_field(n, seed=3, k0=2, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    d0 = oracle.initial_pressure(u)
     with dhit.Box(n, method, "fp64", nu) as b:
         res = b.init_consistent(u, d0, iters)
         got = b.get_populations()
@@ -130,7 +133,7 @@ def test_init_consistent_parity_fp32(method):
     import paper_1601_03815_amd as dhit
     n, nu, iters = 32, 0.01, 20
     u = synth.dhit_field(n, seed=3, k0=2, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    d0 = oracle.initial_pressure(u)
     with dhit.Box(n, method, "fp32", nu) as b:
         b.init_consistent(u, d0, iters)
         got = b.get_populations()
@@ -143,10 +146,11 @@ def test_init_consistent_edge_cases():
     """iters = 0 is init_velocity_field; DUGKS boxes and iters < 0 are
     rejected with their error codes; after the iteration the velocity is the
     prescribed one."""
+    import oracle
     import paper_1601_03815_amd as dhit
     n = 12
     u = synth.dhit_field(n, seed=4, k0=2, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    d0 = oracle.initial_pressure(u)
     with dhit.Box(n, "mrt", "fp64", 0.01) as a, dhit.Box(n, "mrt", "fp64", 0.01) as b:
         a.init_velocity_field(u, d0)
         assert b.init_consistent(u, d0, 0) == 0.0
@@ -177,7 +181,8 @@ def test_iteration_removes_the_remaining_transient(method):
     FP64 oracle gives 0.10 for BGK and 0.18 for MRT on this field)."""
     import paper_1601_03815_amd as dhit
     u = synth.dhit_field(32, seed=2, k0=2, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    with dhit.Box(32, method, "fp64", 0.01) as b:
+        d0 = b.initial_pressure(u)
     div = {}
     for label in ("spectral", "iterated"):
         with dhit.Box(32, method, "fp64", 0.01) as b:
@@ -198,7 +203,7 @@ def test_init_consistent_parity_128():
     import paper_1601_03815_amd as dhit
     n, nu, iters = 128, 0.005, 5
     u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
-    d0 = synth.initial_pressure(u)
+    d0 = oracle.initial_pressure(u)
     with dhit.Box(n, "mrt", "fp64", nu) as b:
         res = b.init_consistent(u, d0, iters)
         got = b.get_populations()
@@ -208,3 +213,32 @@ def test_init_consistent_parity_128():
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     assert abs(res - res_o) <= 1e-12 * np.abs(d0).max()
     assert np.abs(j - u).max() < 1e-15
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [4, 15, 16, 32, 64])
+def test_initial_pressure_parity(n):
+    """The library's spectral pressure (hipFFT) against the oracle's, element
+    by element within 1e-12 of the largest |drho|: odd n (no Nyquist plane)
+    and even n (Nyquist derivative factors dropped on both sides)."""
+    import oracle
+    import paper_1601_03815_amd as dhit
+    u = synth.dhit_field(n, seed=6, k0=max(1.0, n / 8), u_rms=0.05)
+    with dhit.Box(n, "mrt", "fp64", 0.01) as b:
+        got = b.initial_pressure(u)
+    ref = oracle.initial_pressure(u)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.gpu
+def test_initial_pressure_taylor_green_on_the_gpu():
+    """Taylor-Green closed form through the library, rho0 = 1.3 (drho = 3 p
+    with p proportional to rho0)."""
+    import paper_1601_03815_amd as dhit
+    n, U, rho0 = 16, 0.05, 1.3
+    x = synth.grid(n)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    p = rho0 * U * U / 16 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)
+    with dhit.Box(n, "bgk", "fp64", 0.01, rho0=rho0) as b:
+        d = b.initial_pressure(synth.taylor_green(n, U))
+    assert np.abs(d - 3 * p).max() <= 1e-13 * np.abs(3 * p).max()
