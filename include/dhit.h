@@ -307,6 +307,32 @@ enum dhit_kernel {
 int32_t set_kernel_timing(dhit_box *b, int32_t enable);
 int32_t read_kernel_timings(dhit_box *b, double *ms, int64_t *launches);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  One step of the method in *p (LBE: step_lbe's kernel, BGK or
+ * MRT; DUGKS: the fused kernel of step_dugks, variant default only) from
+ * the population field in src to dst, with the same per-step FP64 global
+ * reduction: sums (device double[5], or NULL) receives (sum drho, sum jx,
+ * sum jy, sum jz, 1/2 sum |u|^2) of the new state.  No box is involved:
+ * src and dst are caller-owned device buffers of
+ * population_buffer_bytes(p) bytes each, 256-byte aligned, distinct, laid
+ * out as a box's buffers (19 arrays of the padded stride; LBE: the stored
+ * post-collision phase; DUGKS: f~); p->f_a and p->f_b are ignored.
+ * Work is issued on p->stream (NULL = the null stream), which must belong to
+ * the current device; the call returns without waiting.
+ * The per-block partial sums of the reduction go to a static work space of
+ * the library on the current device (131072 block slots, 5 MiB, held until
+ * the process ends); the call makes no allocation of any kind.  Every call
+ * on one GPU shares that work space: calls whose work overlaps on one GPU
+ * (on different streams, or from different threads) race and must be
+ * ordered by the caller.  Each launch writes every slot it reads, so nothing
+ * has to be cleared between calls.
+ * Errors: DHIT_EINVAL for null pointers, src == dst, misaligned buffers,
+ * invalid parameters (as create_box), the two-pass DUGKS variant, or a box
+ * whose reduction needs more than 131072 block slots (LBE: n > 322);
+ * DHIT_EDEVICE if a launch fails. */
+int32_t step_noalloc(const dhit_params *p, const void *src, void *dst, double *sums);
+
 /* Copy `bytes` bytes (a multiple of 16) between two 16-byte-aligned
  * device buffers on `stream` (a hipStream_t, NULL = the null stream) with a
  * plain streaming copy kernel: the reference for achievable HBM bandwidth

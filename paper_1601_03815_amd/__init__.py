@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, set_mesh, last_error,
     moments, vorticity, initial_pressure, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
-    sums_history, set_kernel_timing, read_kernel_timings, device_copy, KERNEL_NAMES,
+    sums_history, set_kernel_timing, read_kernel_timings, device_copy, step_noalloc, KERNEL_NAMES,
     create_batch, batch_step, batch_info, destroy_batch,
 )
 from . import _binding

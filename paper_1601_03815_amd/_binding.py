@@ -101,6 +101,7 @@ def _load():
         "set_kernel_timing": ([box, i32], i32),
         "read_kernel_timings": ([box, dp, dp], i32),
         "device_copy": ([ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p], i32),
+        "step_noalloc": ([P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], i32),
         "dhit_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -316,10 +317,18 @@ def device_copy(dst_ptr, src_ptr, nbytes, stream_handle=0):
                             ctypes.c_void_p(stream_handle)))
 
 
+def step_noalloc(p, src_ptr, dst_ptr, sums_ptr=None):
+    """One step of the method in params p from device buffer src_ptr to
+    dst_ptr (integers: device addresses), sums to device double[5] at
+    sums_ptr (or None); the library allocates nothing."""
+    _check(_lib.step_noalloc(ctypes.byref(p), ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
+                             None if sums_ptr is None else ctypes.c_void_p(sums_ptr)))
+
+
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
     "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
-    "set_kernel_timing", "read_kernel_timings", "device_copy", "dhit_last_error",
+    "set_kernel_timing", "read_kernel_timings", "device_copy", "step_noalloc", "dhit_last_error",
 ]

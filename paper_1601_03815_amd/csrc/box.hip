@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -140,6 +141,40 @@ void check_finite(const double *s, int count) {
 
 void require_box(const dhit_box *b) {
   if (!b) fail(DHIT_EINVAL, "null box");
+}
+
+}  // namespace
+
+// Work space of step_noalloc: the per-block partial sums of one step's
+// global reduction, plus a slot where the finalisation writes the sums when
+// the caller wants none.  A file-scope device array, so that the entry point
+// allocates nothing; every GPU the library runs on holds its own copy until
+// the process ends.  In host code `scratch` names a host-side stand-in: the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current and kept in g_scratch_ptr.
+constexpr int64_t kNoallocPartials = 131072;                      // block partial slots
+constexpr int64_t kNoallocDoubles = 5 * kNoallocPartials + 8;     // [5][slots] + the discard slot
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+double *scratch_on_current_device() {
+  int dev = 0;
+  DHIT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(DHIT_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    DHIT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(DHIT_EDEVICE, "no device address for the step_noalloc work space");
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -549,6 +584,45 @@ int32_t box_synchronize(dhit_box *b) {
       DHIT_HIP(hipMemcpy(s, b->hist + ((b->steps - 1) % dhit::kHistoryCap) * 5, sizeof(s), hipMemcpyDeviceToHost));
       check_finite(s, 5);
     }
+    return DHIT_OK;
+  });
+}
+
+int32_t step_noalloc(const dhit_params *pp, const void *src, void *dst, double *sums) {
+  return guarded([&]() -> int32_t {
+    if (!pp || !src || !dst) fail(DHIT_EINVAL, "null argument");
+    dhit_params p = *pp;
+    p.f_a = p.f_b = nullptr;  // the caller's buffers come as src and dst
+    validate(p);
+    if (p.method == DHIT_DUGKS && p.variant != DHIT_VARIANT_DEFAULT)
+      fail(DHIT_EINVAL, "step_noalloc runs the fused DUGKS step only (the two-pass form needs a field-sized work space)");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 255)
+      fail(DHIT_EINVAL, "population buffers must be 256-byte aligned");
+    if (src == dst) fail(DHIT_EINVAL, "src and dst must be different buffers");
+    if (p.method == DHIT_DUGKS && p.z_chunk == 0) p.z_chunk = dhit::fused_auto_chunk(p);
+    const int64_t blocks = reduction_blocks(p);
+    if (blocks > kNoallocPartials)
+      fail(DHIT_EINVAL, "box too large for step_noalloc: its reduction needs " + std::to_string(blocks) +
+                            " block partials, the static work space holds " + std::to_string(kNoallocPartials) +
+                            " (LBE: n <= 322)");
+    double *ws = scratch_on_current_device();
+    dhit_box b;  // host-side view of the caller's buffers; owns nothing
+    b.p = p;
+    b.n = p.n;
+    b.ncell = (int64_t)p.n * p.n * p.n;
+    b.elem = p.precision == DHIT_FP32 ? 4 : 8;
+    b.stride = padded_stride(b.ncell, b.elem);
+    b.f[0] = const_cast<void *>(src);
+    b.f[1] = dst;
+    b.stream = static_cast<hipStream_t>(p.stream);
+    b.partials = ws;
+    b.max_blocks = (int)kNoallocPartials;
+    derive_step_params(b);
+    double *out = sums ? sums : ws + 5 * kNoallocPartials;
+    if (p.method == DHIT_DUGKS)
+      dhit::launch_dugks_step(b, src, dst, out);
+    else
+      dhit::launch_lbe_step(b, src, dst, out);
     return DHIT_OK;
   });
 }
