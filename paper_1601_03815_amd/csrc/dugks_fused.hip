@@ -48,7 +48,7 @@
 // 44 values of LDS per column (44 KB for a 32 x 8 tile, two blocks per
 // compute unit).  split_tile (FP64): two threads per column, one in each of
 // two groups that hold about half of the populations each (see below), so
-// that a thread's registers fit two waves per SIMD; 66 values per column.
+// that a thread's registers fit two waves per SIMD; 70 values per column.
 // LDS reads are gathered (see gathered()) so that each chunk of work waits
 // for LDS once.
 //
@@ -110,6 +110,25 @@ constexpr int pid(int a, int b) {
 // Position of a z-moving population among the ten (q5, q6, q11..q18).
 constexpr int zslot(int q) { return q == 5 ? 0 : (q == 6 ? 1 : q - 9); }
 constexpr bool is_diag_z(int q) { return q >= 11; }
+
+// Column of the tile (row-major, ty * W + tx) that thread t of a march
+// handles.  In the 32-wide tile a wavefront covers two rows; the two rows
+// made only of halo columns (0 and 7) are put together in the last
+// wavefront, so that the work of the updated cells (stencils, faces,
+// stores), which halo rows skip, runs on three wavefronts instead of four:
+// wavefronts 0..2 take rows (1, 2), (3, 4), (5, 6) and wavefront 3 rows 0
+// and 7.  A row stays 32 consecutive lanes, as the x-face lane shift needs.
+// Other widths keep row-major order.
+template <int W>
+__device__ __forceinline__ int tile_column(int t) {
+  if constexpr (W == 32) {
+    const int w = t >> 6, half = (t >> 5) & 1, tx = t & 31;
+    const int ty = w < 3 ? 2 * w + 1 + half : (half ? 7 : 0);
+    return ty * 32 + tx;
+  } else {
+    return t;
+  }
+}
 
 // Compiler-only memory fence between the phases of a plane's work: LDS
 // values are re-read after it instead of being kept live in registers
@@ -414,7 +433,7 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   const int n = p.n;
   const int64_t stride = p.stride;
-  const int tid = threadIdx.x;
+  const int tid = tile_column<W>(threadIdx.x);  // column of the tile
   const int tx = tid % TX, ty = tid / TX;
   const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
   const int z1 = min(z0 + nz_chunk, n);
@@ -711,17 +730,22 @@ constexpr int local_of(int q) {
 }
 // LDS per column after the plane buffers:
 //   RA [12]: A's partial moments (read by B after the first barrier of an
-//            iteration), then the moments [0..4) of the y-face between the
-//            column and the next row and the z-face moments [8..12), formed
-//            by B (read by both groups after the third; a column's lower
-//            y-face is the upper one of the column W before it);
+//            iteration), then the z-face moments [8..12), formed by B (read
+//            by A after the third);
 //   RB [10]: B's partial moments, then the x-face moments [0..8) formed by A;
 //   SA [4]:  A's part of the sums of its last stored cell (read by B in the
-//            next iteration).
-// Every reuse is separated from the previous reads by a barrier or by
-// program order within the one thread of the column that does both.
-constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10;
-constexpr int kSplitValues = kSA + 4;
+//            next iteration);
+//   RY [4]:  the moments of the y-face between the column and the next row,
+//            formed by B in the third phase and read after the third barrier
+//            by both threads of the column above (its lower y-face).
+// RA, RB and SA of a column are used only by the two threads of that
+// column, so every reuse is separated from the previous reads by a barrier
+// or by program order within one thread.  RY is read by another column,
+// at the end of an iteration, without a barrier before that column's next
+// partial moments are written: it has slots of its own, next written after
+// the second barrier of the next iteration.
+constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10, kRY = kSA + 4;
+constexpr int kSplitValues = kRY + 4;
 
 // Loads of the group's populations of the column's cell in plane `plane`.
 template <typename Real, int G>
@@ -787,7 +811,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   constexpr int NG = Group<G>::N;
   const int n = p.n;
   const int64_t stride = p.stride;
-  const int c = threadIdx.x - G * NT;  // column of the tile
+  const int c = tile_column<W>(threadIdx.x - G * NT);  // column of the tile
   const int tx = c % TX, ty = c / TX;
   const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
   const int z1 = min(z0 + nz_chunk, n);
@@ -807,6 +831,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   Real *const RA = L + kRA * NT + c;
   Real *const RB = L + kRB * NT + c;
   Real *const SA = L + kSA * NT + c;
+  Real *const RY = L + kRY * NT + c;
 
   Real pf[NG];            // the group's f~ of the plane being published
   Real acc_c[NG];         // centre p-1
@@ -963,7 +988,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           // last (halo row 0 too); the y- face is read back from the row below
           if (yface) {
             face(I0{}, I0{}, fx[0]);
-            static_for<4>([&](auto i) { RA[i * NT] = fx[0][i]; });
+            static_for<4>([&](auto i) { RY[i * NT] = fx[0][i]; });
           }
         }
         if constexpr (G == 0) {
@@ -1002,10 +1027,10 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           // group's populations: its own two faces and the other group's
           Real fo[2][4];
           if constexpr (G == 0) {
-            static_for<4>([&](auto i) { fo[0][i] = RA[i * NT]; fo[1][i] = RA[i * NT - W]; });
+            static_for<4>([&](auto i) { fo[0][i] = RY[i * NT]; fo[1][i] = RY[i * NT - W]; });
           } else {
             static_for<2>([&](auto f) { static_for<4>([&](auto i) { fo[f][i] = RB[(f * 4 + i) * NT]; }); });
-            static_for<4>([&](auto i) { fx[1][i] = RA[i * NT - W]; });
+            static_for<4>([&](auto i) { fx[1][i] = RY[i * NT - W]; });
           }
           using Ip = std::integral_constant<int, 1>;
           using Im = std::integral_constant<int, -1>;
@@ -1100,7 +1125,7 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
 }  // namespace fused
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
-// FP64 (split march, 512 threads): 132 KB of LDS, one block per compute
+// FP64 (split march, 512 threads): 140 KB of LDS, one block per compute
 // unit; FP32 (256 threads): 44 KB of LDS, two blocks per compute unit
 // (two waves per SIMD).
 constexpr int fused_tile_width(int) { return 32; }
