@@ -259,16 +259,21 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * followed by one launch that finalises every box's global sums; the
  * per-box buffer index and step counter are kept on the device, so runs of
  * 8 steps are replayed from one captured hipGraph.  Results equal
- * single-box steps: LBE populations bit for bit, DUGKS populations to
- * rounding (the batched kernel is a separate instantiation of the same
- * per-tile code), global sums to rounding.
+ * single-box steps: populations bit for bit (a single DUGKS box runs the
+ * same work-list kernel on a table of one entry, and the march rounds
+ * alike whatever the z-chunk; a batch of tile width 16 equals boxes of
+ * tile_width 16), global sums to rounding (the chunk decides how the cell
+ * sums are grouped).
  *
  * create_batch: boxes[nbox] must share method and precision (DUGKS boxes the
  * default variant) and appear once.  With autotune != 0 the persistent grid
- * size and the DUGKS work-item z-chunk are chosen by timing uncommitted
- * trial steps on the boxes themselves (their states are left unchanged);
- * choices are cached per process and, if the environment variable
- * DHIT_TUNE_CACHE names a file, read from and appended to it.  Work is
+ * size and, for DUGKS, the column-tile width (16 or 32) and work-item
+ * z-chunk are chosen by timing uncommitted trial steps on the boxes
+ * themselves (their states are left unchanged); choices are cached per
+ * process under (method, precision, compute units of the device, grid
+ * sizes) and, if the environment variable DHIT_TUNE_CACHE names a file,
+ * read from and appended to it (one line per choice: key, grid, chunk,
+ * tile).  Without autotuning a DUGKS batch uses tile width 32.  Work is
  * issued on the first box's stream; the boxes' own streams are synchronised
  * before each batch step and made to wait for it afterwards.  The boxes must
  * outlive the batch.  Synchronous (waits for the boxes' pending work). */
@@ -278,8 +283,9 @@ int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune, dhit_batc
 /* Advance every box of the batch by nsteps >= 0 steps.  Asynchronous. */
 int32_t batch_step(dhit_batch *bt, int32_t nsteps);
 
-/* info[5] = (persistent grid size, DUGKS z-chunk (0 = per-box default),
- * work items per step, steps per graph replay, 1 if autotuned). */
+/* info[6] = (persistent grid size, DUGKS z-chunk (0 = per-box default),
+ * work items per step, steps per graph replay, 1 if autotuned, DUGKS
+ * column-tile width (0 for LBE)). */
 int32_t batch_info(const dhit_batch *bt, int64_t *info);
 
 int32_t destroy_batch(dhit_batch *bt);

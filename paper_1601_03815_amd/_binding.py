@@ -287,10 +287,10 @@ def batch_step(bt, nsteps=1):
 
 
 def batch_info(bt):
-    info = np.zeros(5, dtype=np.int64)
+    info = np.zeros(6, dtype=np.int64)
     _check(_lib.batch_info(bt, _ptr(info)))
     return dict(grid=int(info[0]), chunk=int(info[1]), items=int(info[2]), graph_steps=int(info[3]),
-                tuned=bool(info[4]))
+                tuned=bool(info[4]), tile=int(info[5]))
 
 
 def destroy_batch(bt):

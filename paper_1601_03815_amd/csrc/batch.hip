@@ -8,9 +8,10 @@
 // captured steps is replayed for long runs.  The persistent grid size (and
 // for DUGKS the z-chunk length of a work item) are chosen per batch by
 // timing candidate settings on the batch itself (uncommitted trial steps,
-// which leave every box's state unchanged); choices are cached per process
-// by (method, precision, grid sizes) and can be shared through a file named
-// by the environment variable DHIT_TUNE_CACHE.
+// which leave every box's state unchanged), for DUGKS together with the
+// column-tile width (16 or 32) of the fused kernel; choices are cached per
+// process by (method, precision, compute units, grid sizes) and can be
+// shared through a file named by the environment variable DHIT_TUNE_CACHE.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -34,6 +35,7 @@ struct dhit_batch {
   int total_items = 0;
   int grid = 0;
   int chunk = 0;  // DUGKS z-chunk of a work item (0 = per-box default)
+  int tile = 32;  // DUGKS column-tile width of the batch's kernel (16 or 32)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -52,14 +54,19 @@ int cu_count() {
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;  // key -> (grid, chunk)
+struct TuneChoice {
+  int grid, chunk, tile;
+};
+std::map<std::string, TuneChoice> g_tune_cache;  // key -> choice
 bool g_tune_file_read = false;
 
+// Cache key: method, precision, the device's compute-unit count (grid sizes
+// are multiples of it) and the sorted grid sizes of the boxes.
 std::string tune_key(const dhit_batch &bt) {
   std::vector<int> ns;
   for (auto *b : bt.boxes) ns.push_back(b->n);
   std::sort(ns.begin(), ns.end());
-  std::string k = std::to_string(bt.method) + "/" + std::to_string(bt.precision) + "/";
+  std::string k = std::to_string(bt.method) + "/" + std::to_string(bt.precision) + "/cu" + std::to_string(cu_count()) + "/";
   for (size_t i = 0; i < ns.size(); ++i) k += (i ? "," : "") + std::to_string(ns[i]);
   return k;
 }
@@ -72,17 +79,18 @@ void read_tune_file() {
   FILE *f = std::fopen(path, "r");
   if (!f) return;
   char key[4096];
-  int grid, chunk;
-  while (std::fscanf(f, "%4095s %d %d", key, &grid, &chunk) == 3) g_tune_cache[key] = {grid, chunk};
+  int grid, chunk, tile;
+  while (std::fscanf(f, "%4095s %d %d %d", key, &grid, &chunk, &tile) == 4)
+    if (grid > 0 && chunk >= 0 && (tile == 16 || tile == 32)) g_tune_cache[key] = {grid, chunk, tile};
   std::fclose(f);
 }
 
-void write_tune_entry(const std::string &key, int grid, int chunk) {
+void write_tune_entry(const std::string &key, const TuneChoice &c) {
   const char *path = std::getenv("DHIT_TUNE_CACHE");
   if (!path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), grid, chunk);
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), c.grid, c.chunk, c.tile);
   std::fclose(f);
 }
 
@@ -103,7 +111,7 @@ void build_table(dhit_batch &bt, int chunk) {
     if (bt.method == DHIT_DUGKS) {
       const int cz = chunk > 0 ? std::min(chunk, b->n) : dhit::fused_default_chunk(b->n);
       d.nz_chunk = cz;
-      d.items = dhit::fused_dugks_items(b->n, bt.precision, cz, &d.tiles_x, &d.tiles_y);
+      d.items = dhit::fused_dugks_items(b->n, bt.tile, cz, &d.tiles_x, &d.tiles_y);
     } else {
       d.items = dhit::cell_blocks(b->ncell);
     }
@@ -140,7 +148,7 @@ void upload_table(dhit_batch &bt) {
 void enqueue_step(dhit_batch &bt, int commit) {
   const int nbox = (int)bt.boxes.size();
   if (bt.method == DHIT_DUGKS)
-    dhit::launch_dugks_batch(bt.stream, bt.precision, bt.d_boxes, nbox, bt.total_items, bt.grid);
+    dhit::launch_dugks_batch(bt.stream, bt.precision, bt.tile, bt.d_boxes, nbox, bt.total_items, bt.grid);
   else
     dhit::launch_lbe_batch(bt.stream, bt.method, bt.precision, bt.d_boxes, nbox, bt.total_items, bt.grid);
   dhit::launch_finalize_batch(bt.stream, bt.d_boxes, nbox, commit);
@@ -194,44 +202,52 @@ float time_trial(dhit_batch &bt, int reps) {
   return ms / reps;
 }
 
+// Chooses the persistent grid size and, for DUGKS, the column-tile width
+// and the z-chunk of a work item, by timing each combination on the batch.
 void autotune(dhit_batch &bt) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   read_tune_file();
   const std::string key = tune_key(bt);
   auto it = g_tune_cache.find(key);
   if (it != g_tune_cache.end()) {
-    bt.grid = it->second.first;
-    build_table(bt, it->second.second);
+    bt.grid = it->second.grid;
+    bt.tile = it->second.tile;
+    build_table(bt, it->second.chunk);
     bt.tuned = true;
     return;
   }
   const int cus = cu_count();
-  std::vector<int> grids, chunks;
+  std::vector<int> grids, chunks, tiles;
   if (bt.method == DHIT_DUGKS) {
     grids = {cus, 2 * cus, 4 * cus};
     chunks = {8, 16, 32};
+    tiles = {32, 16};
   } else {
     grids = {2 * cus, 4 * cus, 8 * cus, 16 * cus, 32 * cus};
     chunks = {0};
+    tiles = {bt.tile};
   }
   float best = 1e30f;
-  int best_grid = grids[0], best_chunk = chunks[0];
-  for (int c : chunks) {
-    build_table(bt, c);
-    for (int g : grids) {
-      bt.grid = std::min(g, std::max(1, bt.total_items));
-      const float ms = time_trial(bt, 3);
-      if (ms < best) {
-        best = ms;
-        best_grid = bt.grid;
-        best_chunk = c;
+  TuneChoice choice{grids[0], chunks[0], tiles[0]};
+  for (int w : tiles) {
+    bt.tile = w;
+    for (int c : chunks) {
+      build_table(bt, c);
+      for (int g : grids) {
+        bt.grid = std::min(g, std::max(1, bt.total_items));
+        const float ms = time_trial(bt, 3);
+        if (ms < best) {
+          best = ms;
+          choice = {bt.grid, c, w};
+        }
       }
     }
   }
-  bt.grid = best_grid;
-  build_table(bt, best_chunk);
-  g_tune_cache[key] = {best_grid, best_chunk};
-  write_tune_entry(key, best_grid, best_chunk);
+  bt.grid = choice.grid;
+  bt.tile = choice.tile;
+  build_table(bt, choice.chunk);
+  g_tune_cache[key] = choice;
+  write_tune_entry(key, choice);
   bt.tuned = true;
 }
 
@@ -263,6 +279,7 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
     bt->method = boxes[0]->p.method;
     bt->precision = boxes[0]->p.precision;
     bt->stream = boxes[0]->stream;
+    bt->tile = dhit::fused_tile_width_of(bt->precision);
     if (hipMalloc(&bt->d_boxes, nbox * sizeof(dhit::BatchBox)) != hipSuccess ||
         hipMalloc(&bt->d_trial, nbox * dhit::kNumSums * sizeof(double)) != hipSuccess)
       throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");
@@ -357,6 +374,7 @@ int32_t batch_info(const dhit_batch *bt, int64_t *info) {
     info[2] = bt->total_items;
     info[3] = kGraphSteps;
     info[4] = bt->tuned ? 1 : 0;
+    info[5] = bt->method == DHIT_DUGKS ? bt->tile : 0;
     return DHIT_OK;
   });
 }

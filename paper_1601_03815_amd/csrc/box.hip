@@ -123,6 +123,11 @@ int64_t scratch_bytes_of(const dhit_params &p, int64_t pop_bytes) {
   return (p.method == DHIT_DUGKS && p.variant == DHIT_VARIANT_TWO_PASS) ? pop_bytes : 0;
 }
 
+// The fused DUGKS step's one-box tables (see fused_table_entries).
+int64_t fused_table_bytes(const dhit_params &p) {
+  return (p.method == DHIT_DUGKS && p.variant == DHIT_VARIANT_DEFAULT) ? 2 * (int64_t)sizeof(dhit::BatchBox) : 0;
+}
+
 // Blocks (and so partial-sum slots) of the largest per-step launch.
 int64_t reduction_blocks(const dhit_params &p) {
   const int64_t ncell = (int64_t)p.n * p.n * p.n;
@@ -153,7 +158,8 @@ void require_box(const dhit_box *b) {
 // device address comes from hipGetSymbolAddress, taken once per device with
 // that device current and kept in g_scratch_ptr.
 constexpr int64_t kNoallocPartials = 131072;                      // block partial slots
-constexpr int64_t kNoallocDoubles = 5 * kNoallocPartials + 8;     // [5][slots] + the discard slot
+constexpr int64_t kNoallocTable = 5 * kNoallocPartials + 8;        // offset of the fused-step tables
+constexpr int64_t kNoallocDoubles = kNoallocTable + (2 * sizeof(dhit::BatchBox) + 7) / 8;
 static __device__ __align__(256) double scratch[kNoallocDoubles];
 
 namespace {
@@ -224,7 +230,8 @@ int64_t population_buffer_bytes(const dhit_params *p) {
 int64_t box_bytes(const dhit_params *p) {
   int64_t pop = population_buffer_bytes(p);
   if (pop < 0) return pop;
-  return 2 * pop + reduction_blocks(*p) * 5 * 8 + dhit::kHistoryCap * 5 * 8 + scratch_bytes_of(*p, pop);
+  return 2 * pop + reduction_blocks(*p) * 5 * 8 + dhit::kHistoryCap * 5 * 8 + scratch_bytes_of(*p, pop) +
+         fused_table_bytes(*p);
 }
 
 int32_t create_box(const dhit_params *pp, dhit_box **out) {
@@ -265,6 +272,14 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
           fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
       }
       derive_step_params(*b);
+      if (fused_table_bytes(b->p) > 0) {
+        if (hipMalloc(&b->fused_table, (size_t)fused_table_bytes(b->p)) != hipSuccess)
+          fail(DHIT_ENOMEM, "cannot allocate the fused-step table");
+        b->own_fused_table = true;
+        dhit::BatchBox e[2];
+        dhit::fused_table_entries(*b, e);
+        DHIT_HIP(hipMemcpy(b->fused_table, e, sizeof(e), hipMemcpyHostToDevice));
+      }
       // zero state until initialised
       DHIT_HIP(hipMemsetAsync(b->f[0], 0, pop, b->stream));
       DHIT_HIP(hipMemsetAsync(b->hist, 0, (size_t)dhit::kHistoryCap * 5 * sizeof(double), b->stream));
@@ -291,6 +306,7 @@ int32_t destroy_box(dhit_box *b) {
   if (b->hist) (void)hipFree(b->hist);
   if (b->scratch) (void)hipFree(b->scratch);
   if (b->mesh) (void)hipFree(b->mesh);
+  if (b->own_fused_table && b->fused_table) (void)hipFree(b->fused_table);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return DHIT_OK;
@@ -619,8 +635,15 @@ int32_t step_noalloc(const dhit_params *pp, const void *src, void *dst, double *
     b.max_blocks = (int)kNoallocPartials;
     derive_step_params(b);
     double *out = sums ? sums : ws + 5 * kNoallocPartials;
-    if (p.method == DHIT_DUGKS)
+    if (p.method == DHIT_DUGKS) {
+      // the fused step reads the box as a table in device memory: written
+      // into the work space by a launch that carries the entries by value
+      dhit::BatchBox e[2];
+      dhit::fused_table_entries(b, e);
+      b.fused_table = reinterpret_cast<dhit::BatchBox *>(ws + kNoallocTable);
+      dhit::launch_store_table(b.stream, e, b.fused_table);
       dhit::launch_dugks_step(b, src, dst, out);
+    }
     else
       dhit::launch_lbe_step(b, src, dst, out);
     return DHIT_OK;

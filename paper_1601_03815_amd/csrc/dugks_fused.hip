@@ -58,6 +58,8 @@
 // ring (loads only).  Blocks are numbered so that the tiles one XCD (one L2)
 // works on at a time are neighbours, whose halo columns then come from that
 // L2.
+#include <cstring>
+
 #include "collision.hpp"
 
 namespace dhit {
@@ -659,28 +661,14 @@ constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
 // (b mod 8) * padded/8 + b/8.
 __device__ __forceinline__ int xcd_tile(int b, int padded) { return (b & 7) * (padded >> 3) + (b >> 3); }
 
+// One launch advances one or many boxes: work item = one tile z-chunk of
+// one box of the device table `boxes` (sorted by item_begin), numbered as
+// the tiles of that box's own launch.  Round r of the grid takes items
+// [r G, (r+1) G), dealt to the XCDs in contiguous eighths.  A single box is
+// a table of one entry, so a box stepped alone and the same box stepped in
+// a batch run the same machine code and give the same bits.
 template <typename Real, int W>
-__global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_kernel(const Real *__restrict__ ft, Real *__restrict__ out,
-                                                                  StepParams p, int tiles_x, int tiles_y,
-                                                                  int nz_chunk, int ntiles, double *__restrict__ partials) {
-  __shared__ Real L[kFusedValues * Tile<W>::NT];
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= ntiles) return;
-  const int bx = t % tiles_x;
-  const int by = (t / tiles_x) % tiles_y;
-  const int bz = t / (tiles_x * tiles_y);
-  double v[kNumSums] = {0, 0, 0, 0, 0};
-  fused_tile<Real, W>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
-  // the march ends with a barrier: L is free for the block reduction
-  write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
-}
-
-// Many boxes in one persistent launch: work item = one tile z-chunk of one
-// box, numbered as the tiles of that box's single-box launch.  Round r of
-// the grid takes items [r G, (r+1) G), dealt to the XCDs in contiguous
-// eighths.
-template <typename Real, int W>
-__global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
+__global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_kernel(const BatchBox *__restrict__ boxes, int nbox,
                                                                   int total_items) {
   __shared__ Real L[kFusedValues * Tile<W>::NT];
   const int G = gridDim.x;
@@ -696,6 +684,7 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_batch_
     double v[kNumSums] = {0, 0, 0, 0, 0};
     fused_tile<Real, W>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp, bx, by, bz,
                         d.nz_chunk, L, v);
+    // the march ends with a barrier: L is free for the block reduction
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
   }
@@ -1077,28 +1066,10 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   __syncthreads();
 }
 
+// Work-list kernel of the split march (see dugks_fused_kernel).
 template <typename Real, int W>
-__global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const Real *__restrict__ ft,
-                                                                      Real *__restrict__ out, StepParams p,
-                                                                      int tiles_x, int tiles_y, int nz_chunk,
-                                                                      int ntiles, double *__restrict__ partials) {
-  __shared__ Real L[kSplitValues * Tile<W>::NT];
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= ntiles) return;
-  const int bx = t % tiles_x;
-  const int by = (t / tiles_x) % tiles_y;
-  const int bz = t / (tiles_x * tiles_y);
-  double v[kNumSums] = {0, 0, 0, 0, 0};
-  if (threadIdx.x < Tile<W>::NT)
-    split_tile<Real, W, 0>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
-  else
-    split_tile<Real, W, 1>(to_global(ft), to_global(out), p, bx, by, bz, nz_chunk, L, v);
-  write_block_partials(v, partials, ntiles, t, reinterpret_cast<double (*)[kNumSums]>(L));
-}
-
-template <typename Real, int W>
-__global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(BatchBox *__restrict__ boxes, int nbox,
-                                                                            int total_items) {
+__global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const BatchBox *__restrict__ boxes, int nbox,
+                                                                      int total_items) {
   __shared__ Real L[kSplitValues * Tile<W>::NT];
   const int G = gridDim.x;
   for (int base = 0; base < total_items; base += G) {
@@ -1122,6 +1093,15 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_batch_kernel(Batc
   }
 }
 
+// Writes table entries given by value (the launch carries them in its
+// arguments), for callers that must not copy from host memory.
+__global__ void store_table_kernel(BatchBox e0, BatchBox e1, BatchBox *__restrict__ dst) {
+  if (threadIdx.x == 0) {
+    dst[0] = e0;
+    dst[1] = e1;
+  }
+}
+
 }  // namespace fused
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
@@ -1132,8 +1112,8 @@ constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
 
-int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_y) {
-  const int ix = fused_tile_width(precision) - 2, iy = 8 - 2;
+int fused_dugks_items(int n, int w, int chunk, int *tiles_x, int *tiles_y) {
+  const int ix = w - 2, iy = 8 - 2;
   const int tx = (n + ix - 1) / ix;
   const int ty = (n + iy - 1) / iy;
   if (tiles_x) *tiles_x = tx;
@@ -1152,16 +1132,10 @@ constexpr int kMinAutoChunk = 8;
 int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
   const int n = p.n;
   const int w = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
-  const int ix = w - 2, iy = 8 - 2;
-  const int tx = (n + ix - 1) / ix;
-  const int ty = (n + iy - 1) / iy;
   const int cz = p.z_chunk ? p.z_chunk : std::min(n, kMinAutoChunk);
-  const int nzc = (n + cz - 1) / cz;
   if (width) *width = w;
-  if (tiles_x) *tiles_x = tx;
-  if (tiles_y) *tiles_y = ty;
   if (nz_chunk) *nz_chunk = cz;
-  return tx * ty * nzc;
+  return fused_dugks_items(n, w, cz, tiles_x, tiles_y);
 }
 
 // FP64 tiles use the split-population march (two thread groups per
@@ -1170,27 +1144,66 @@ template <typename Real>
 constexpr bool kSplit = sizeof(Real) == 8;
 
 template <typename Real, int W>
-static void fused_launch(dhit_box &b, const void *src, void *dst, int tiles, int tx, int ty, int cz) {
-  const int grid = (tiles + 7) / 8 * 8;
+static void list_launch(hipStream_t s, const BatchBox *d_boxes, int nbox, int total_items, int grid) {
+  grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8
   if constexpr (kSplit<Real>)
-    hipLaunchKernelGGL((fused::dugks_split_kernel<Real, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, b.stream,
-                       static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
+    hipLaunchKernelGGL((fused::dugks_split_kernel<Real, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, s, d_boxes,
+                       nbox, total_items);
   else
-    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, b.stream,
-                       static_cast<const Real *>(src), static_cast<Real *>(dst), b.sp, tx, ty, cz, tiles, b.partials);
+    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes, nbox,
+                       total_items);
 }
 
-template <typename Real>
+void launch_dugks_batch(hipStream_t s, int precision, int w, const BatchBox *d_boxes, int nbox, int total_items,
+                        int grid) {
+  if (w != 16 && w != 32) throw Error(DHIT_EINVAL, "fused DUGKS tile width must be 16 or 32");
+  if (precision == DHIT_FP64) {
+    if (w == 16) list_launch<double, 16>(s, d_boxes, nbox, total_items, grid);
+    else list_launch<double, 32>(s, d_boxes, nbox, total_items, grid);
+  } else {
+    if (w == 16) list_launch<float, 16>(s, d_boxes, nbox, total_items, grid);
+    else list_launch<float, 32>(s, d_boxes, nbox, total_items, grid);
+  }
+  DHIT_HIP(hipGetLastError());
+}
+
+// The two one-box tables of a box: entry c steps from f[c] to f[1 - c].
+void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]) {
+  int w, tx, ty, cz;
+  const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
+  for (int c = 0; c < 2; ++c) {
+    std::memset(&e[c], 0, sizeof(BatchBox));
+    e[c].f[0] = b.f[0];
+    e[c].f[1] = b.f[1];
+    e[c].sp = b.sp;
+    e[c].ncell = (int)b.ncell;
+    e[c].item_begin = 0;
+    e[c].items = tiles;
+    e[c].tiles_x = tx;
+    e[c].tiles_y = ty;
+    e[c].nz_chunk = cz;
+    e[c].partials = b.partials;
+    e[c].hist = b.hist;
+    e[c].cur = c;
+  }
+}
+
+void launch_store_table(hipStream_t s, const BatchBox (&e)[2], BatchBox *dst) {
+  hipLaunchKernelGGL(fused::store_table_kernel, dim3(1), dim3(64), 0, s, e[0], e[1], dst);
+  DHIT_HIP(hipGetLastError());
+}
+
 static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
+  if (!b.fused_table) throw Error(DHIT_EINVAL, "box has no fused-step table");
+  int entry;
+  if (src == b.f[0] && dst == b.f[1]) entry = 0;
+  else if (src == b.f[1] && dst == b.f[0]) entry = 1;
+  else throw Error(DHIT_EINVAL, "fused DUGKS step between buffers that are not the box's");
   int w, tx, ty, cz;
   const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
-    if (w == 16)
-      fused_launch<Real, 16>(b, src, dst, tiles, tx, ty, cz);
-    else
-      fused_launch<Real, 32>(b, src, dst, tiles, tx, ty, cz);
-    DHIT_HIP(hipGetLastError());
+    launch_dugks_batch(b.stream, b.p.precision, w, b.fused_table + entry, 1, tiles, tiles);
     t.done();
   }
   launch_finalize_sums(b, b.partials, tiles, sums_out);
@@ -1251,25 +1264,6 @@ int fused_auto_chunk(const dhit_params &p) {
   return fused_balanced_chunk(p.n, tx * ty, std::max(cus, 1) * fused_resident_blocks(p.precision, w));
 }
 
-void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid) {
-  grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8
-  if (precision == DHIT_FP64) {
-    constexpr int W = fused_tile_width(DHIT_FP64);
-    hipLaunchKernelGGL((fused::dugks_split_batch_kernel<double, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, s,
-                       d_boxes, nbox, total_items);
-  } else {
-    constexpr int W = fused_tile_width(DHIT_FP32);
-    hipLaunchKernelGGL((fused::dugks_batch_kernel<float, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
-                       nbox, total_items);
-  }
-  DHIT_HIP(hipGetLastError());
-}
-
-void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out) {
-  if (b.p.precision == DHIT_FP64)
-    fused_step<double>(b, src, dst, sums_out);
-  else
-    fused_step<float>(b, src, dst, sums_out);
-}
+void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out) { fused_step(b, src, dst, sums_out); }
 
 }  // namespace dhit

@@ -112,6 +112,8 @@ struct dhit_box {
   int64_t steps = 0;
   void *scratch = nullptr;     // DUGKS two-pass transform field
   double *mesh = nullptr;      // stretched-mesh tables [3][kMeshTables][n] (DUGKS), NULL = unit cells
+  dhit::BatchBox *fused_table = nullptr;  // fused DUGKS step: the box as a one-entry table, per buffer phase [2]
+  bool own_fused_table = false;
   dhit::StepParams sp{};
   dhit::SpectrumWork *spec = nullptr;
   dhit::KernelTimer *timer = nullptr;
@@ -144,13 +146,20 @@ void launch_velocity(dhit_box &b, const void *f, double *d_u);   // u = j / rho0
 // Batched launches (batch.hip drives them)
 void launch_lbe_batch(hipStream_t s, int method, int precision, BatchBox *d_boxes, int nbox, int total_items,
                       int grid);
-void launch_dugks_batch(hipStream_t s, int precision, BatchBox *d_boxes, int nbox, int total_items, int grid);
+// One launch of the fused DUGKS kernel (tile width w) over the work items
+// of a device table of boxes; a single box is a table of one entry.
+void launch_dugks_batch(hipStream_t s, int precision, int w, const BatchBox *d_boxes, int nbox, int total_items,
+                        int grid);
+// The two one-entry tables of a box (entry c steps from f[c] to f[1 - c]),
+// and a launch that writes two entries given by value to device memory.
+void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]);
+void launch_store_table(hipStream_t s, const BatchBox (&e)[2], BatchBox *dst);
 void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commit);
 int fused_tile_width_of(int precision);
 int fused_default_chunk(int n);
 int fused_balanced_chunk(int n, int tiles_xy, int slots);
 int fused_auto_chunk(const dhit_params &p);
-int fused_dugks_items(int n, int precision, int chunk, int *tiles_x, int *tiles_y);
+int fused_dugks_items(int n, int w, int chunk, int *tiles_x, int *tiles_y);
 
 // Spectrum (spectrum.hip)
 void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);

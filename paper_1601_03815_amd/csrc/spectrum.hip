@@ -1,6 +1,7 @@
 // Energy spectrum and velocity-derivative statistics of a box (Sec. III):
 //   u = j/rho0 -> u_hat = DFT(u)/n^3 (hipFFT, real-to-complex, batch of 3)
 //   -> shell binning of 1/2 |u_hat|^2 and of |kappa|^2 1/2 |u_hat|^2
+//      (exact integer sums, so E(k) is the same bits on every run)
 //   -> spectral derivatives i kappa_a u_hat_a (inverse transforms)
 //   -> <(d_a u_a)^m>, m = 2, 3, 4 -> K, eps, S, F.
 #include <cmath>
@@ -19,7 +20,8 @@ struct SpectrumWork {
   double *u = nullptr;
   hipfftDoubleComplex *uh = nullptr;
   hipfftDoubleComplex *tmp = nullptr;
-  double *shells = nullptr;    // [2][nshell]: E and kappa^2-weighted E
+  unsigned long long *shells = nullptr;  // [2][kShellParts][nshell]: digit sums of E and kappa^2-weighted E
+  int *overflow = nullptr;               // set when a shell term is out of range or not finite
   double *partials = nullptr;  // [5][blocks]
   double *dstats = nullptr;    // [3][5]
   hipfftHandle fwd = 0, inv = 0;
@@ -35,16 +37,48 @@ struct SpectrumWork {
 // Signed integer wavenumber of FFT index i (numpy fftfreq order).
 __device__ __forceinline__ int signed_k(int i, int n) { return (i <= (n - 1) / 2) ? i : i - n; }
 
-// One thread per mode of the half spectrum; block histogram in LDS, then
-// one atomic add per shell and block.  Modes 0 < kx < n/2 stand for their
-// Hermitian partners too (weight 2).
+// Shell sums are accumulated exactly, so that E(k) does not depend on the
+// order in which threads add their modes: a term e (>= 0) is taken as the
+// integer floor(e 2^kShellFrac), split into three kShellDigit-bit digits,
+// and each digit is summed with integer atomic adds (associative, so the
+// order does not matter).  The host joins the digits in 128-bit integers
+// and rounds once.  Terms below 2^-kShellFrac (3e-27) in absolute value are
+// truncated; a term of 2^8 or more (or not finite; velocities of order one
+// in lattice units already mean a blown-up run) raises the overflow flag.
+// With 34-bit digits a digit sum stays below 2^64, and the joined value
+// below 2^126, for up to 2^30 modes (n <= 1024).
+constexpr int kShellFrac = 88, kShellDigit = 34, kShellParts = 3;
+
+__device__ __forceinline__ void shell_digits(double e, unsigned long long (&d)[kShellParts], bool &over) {
+  if (!(e >= 0.0 && e < 256.0)) {
+    over = true;
+    d[0] = d[1] = d[2] = 0;
+    return;
+  }
+  const double x = e * 0x1p88;                 // exact: a power of two, x < 2^96
+  const double hi = floor(x * 0x1p-68);        // < 2^28
+  const double r = x - hi * 0x1p68;            // exact: a multiple of ulp(x) below 2^68
+  const double mid = floor(r * 0x1p-34);       // < 2^34
+  const double lo = floor(r - mid * 0x1p34);   // < 2^34; drops bits below 2^-88 of e
+  d[2] = (unsigned long long)hi;
+  d[1] = (unsigned long long)mid;
+  d[0] = (unsigned long long)lo;
+}
+
+// One thread per mode of the half spectrum; block histogram of the digits
+// in LDS, then one integer atomic add per digit, shell and block.  Modes
+// 0 < kx < n/2 stand for their Hermitian partners too (weight 2).
+// shells: [2][kShellParts][nshell] digit sums of E and of kappa^2 E.
 __global__ __launch_bounds__(256) void bin_kernel(const hipfftDoubleComplex *__restrict__ uh, int n, int64_t nhalf,
-                                                  int nshell, double inv_n6, double *__restrict__ shells) {
-  extern __shared__ double hist[];  // [2][nshell]
-  for (int i = threadIdx.x; i < 2 * nshell; i += blockDim.x) hist[i] = 0.0;
+                                                  int nshell, double inv_n6, unsigned long long *__restrict__ shells,
+                                                  int *__restrict__ overflow) {
+  extern __shared__ unsigned long long hist[];  // [2][kShellParts][nshell]
+  const int nh = 2 * kShellParts * nshell;
+  for (int i = threadIdx.x; i < nh; i += blockDim.x) hist[i] = 0ull;
   __syncthreads();
   const int nxh = n / 2 + 1;
   const double kfac = 2.0 * M_PI / n;
+  bool over = false;
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nhalf; m += (int64_t)gridDim.x * blockDim.x) {
     const int kxh = (int)(m % nxh);
     const int64_t r = m / nxh;
@@ -59,12 +93,18 @@ __global__ __launch_bounds__(256) void bin_kernel(const hipfftDoubleComplex *__r
     e *= 0.5 * inv_n6 * (self ? 1.0 : 2.0);
     const int k2 = kx * kx + ky * ky + kz * kz;
     const int s = (int)rint(sqrt((double)k2));
-    atomicAdd(&hist[s], e);
-    atomicAdd(&hist[nshell + s], kfac * kfac * (double)k2 * e);
+    unsigned long long d[kShellParts], dk[kShellParts];
+    shell_digits(e, d, over);
+    shell_digits(kfac * kfac * (double)k2 * e, dk, over);
+    for (int j = 0; j < kShellParts; ++j) {
+      if (d[j]) atomicAdd(&hist[j * nshell + s], d[j]);
+      if (dk[j]) atomicAdd(&hist[(kShellParts + j) * nshell + s], dk[j]);
+    }
   }
+  if (over) atomicOr(overflow, 1);
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * nshell; i += blockDim.x)
-    if (hist[i] != 0.0) atomicAdd(&shells[i], hist[i]);
+  for (int i = threadIdx.x; i < nh; i += blockDim.x)
+    if (hist[i] != 0ull) atomicAdd(&shells[i], hist[i]);
 }
 
 // tmp = i kappa_a u_hat_a on the half spectrum; the Nyquist wavenumber of
@@ -200,7 +240,8 @@ static void ensure_work(dhit_box &b) {
   if (hipMalloc(&w->u, 3 * b.ncell * sizeof(double)) != hipSuccess ||
       hipMalloc(&w->uh, 3 * w->nhalf * sizeof(hipfftDoubleComplex)) != hipSuccess ||
       hipMalloc(&w->tmp, w->nhalf * sizeof(hipfftDoubleComplex)) != hipSuccess ||
-      hipMalloc(&w->shells, 2 * w->nshell * sizeof(double)) != hipSuccess ||
+      hipMalloc(&w->shells, 2 * kShellParts * w->nshell * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&w->overflow, sizeof(int)) != hipSuccess ||
       hipMalloc(&w->partials, 5 * 1024 * sizeof(double)) != hipSuccess ||
       hipMalloc(&w->dstats, 3 * 5 * sizeof(double)) != hipSuccess)
     throw Error(DHIT_ENOMEM, "cannot allocate spectrum work space");
@@ -220,6 +261,7 @@ void spectrum_free(dhit_box &b) {
   if (w->uh) (void)hipFree(w->uh);
   if (w->tmp) (void)hipFree(w->tmp);
   if (w->shells) (void)hipFree(w->shells);
+  if (w->overflow) (void)hipFree(w->overflow);
   if (w->partials) (void)hipFree(w->partials);
   if (w->dstats) (void)hipFree(w->dstats);
   delete w;
@@ -234,12 +276,14 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
   DHIT_FFT(hipfftSetStream(w.inv, b.stream));
   launch_velocity(b, b.f[b.cur], w.u);
   DHIT_FFT(hipfftExecD2Z(w.fwd, w.u, w.uh));
-  DHIT_HIP(hipMemsetAsync(w.shells, 0, 2 * w.nshell * sizeof(double), b.stream));
+  const size_t shell_words = 2 * kShellParts * (size_t)w.nshell;
+  DHIT_HIP(hipMemsetAsync(w.shells, 0, shell_words * sizeof(unsigned long long), b.stream));
+  DHIT_HIP(hipMemsetAsync(w.overflow, 0, sizeof(int), b.stream));
   const double inv_n3 = 1.0 / ((double)n * n * n);
   {
     const int blocks = (int)std::min<int64_t>((w.nhalf + 255) / 256, 2048);
-    hipLaunchKernelGGL(bin_kernel, dim3(blocks), dim3(256), 2 * w.nshell * sizeof(double), b.stream, w.uh, n,
-                       w.nhalf, w.nshell, inv_n3 * inv_n3, w.shells);
+    hipLaunchKernelGGL(bin_kernel, dim3(blocks), dim3(256), shell_words * sizeof(unsigned long long), b.stream, w.uh,
+                       n, w.nhalf, w.nshell, inv_n3 * inv_n3, w.shells, w.overflow);
     DHIT_HIP(hipGetLastError());
   }
   for (int a = 0; a < 3; ++a) {
@@ -252,11 +296,24 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
     DHIT_HIP(hipGetLastError());
     launch_finalize_sums(b, w.partials, rb, w.dstats + 5 * a);
   }
-  std::vector<double> sh(2 * w.nshell);
+  std::vector<unsigned long long> dig(shell_words);
   double ds[15];
-  DHIT_HIP(hipMemcpyAsync(sh.data(), w.shells, sh.size() * sizeof(double), hipMemcpyDeviceToHost, b.stream));
+  int over = 0;
+  DHIT_HIP(hipMemcpyAsync(dig.data(), w.shells, shell_words * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          b.stream));
   DHIT_HIP(hipMemcpyAsync(ds, w.dstats, sizeof(ds), hipMemcpyDeviceToHost, b.stream));
+  DHIT_HIP(hipMemcpyAsync(&over, w.overflow, sizeof(int), hipMemcpyDeviceToHost, b.stream));
   DHIT_HIP(hipStreamSynchronize(b.stream));
+  if (over) throw Error(DHIT_ENONFINITE, "velocity field is not finite (or a spectral term exceeds 2^8)");
+  // join the digits of each shell: sum_j digit_j 2^(34 j), then times 2^-88
+  std::vector<double> sh(2 * w.nshell);
+  for (int q = 0; q < 2; ++q)
+    for (int k = 0; k < w.nshell; ++k) {
+      unsigned __int128 v = 0;
+      for (int j = kShellParts - 1; j >= 0; --j)
+        v = (v << kShellDigit) + (unsigned __int128)dig[((size_t)q * kShellParts + j) * w.nshell + k];
+      sh[(size_t)q * w.nshell + k] = std::ldexp((double)v, -kShellFrac);
+    }
   for (int k = 0; k <= kmax; ++k) E_host[k] = k < w.nshell ? sh[k] : 0.0;
   if (stats_host) {
     double K = 0, D = 0;

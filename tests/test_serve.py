@@ -130,10 +130,13 @@ def test_prepare_is_called_once_per_request_after_arrival_before_start():
 @pytest.mark.gpu
 def test_result_is_the_same_alone_and_in_the_mix():
     """Runs served together (continuous batching, both methods overlapping on
-    two streams) give the same spectra as each run alone on its own box.
-    LBE populations are identical bit for bit, so LBE spectra agree to the
-    shell sums' own summation order (atomic adds, ~1e-16); DUGKS spectra
-    agree to FP32 rounding."""
+    two streams) give the same result as each run alone on its own box, bit
+    for bit: the batched kernels equal the single-box ones bit for bit, and
+    the spectrum's shell sums are exact integer sums.  A few served runs are
+    also checked against the FP64 oracle (same initial field, same steps):
+    the FP32 spectrum within 1e-4 of the oracle's at every shell holding at
+    least 1e-10 of the largest, K within 1e-5."""
+    import oracle as O
     import paper_1601_03815_amd as dhit
     import synth
     from paper_1601_03815_amd.serve import GpuBackend
@@ -145,14 +148,33 @@ def test_result_is_the_same_alone_and_in_the_mix():
     be.close()
     assert stats["requests"] == len(trace)
     for r in trace:
+        u = synth.dhit_field(r.n, seed=r.seed, k0=4.0, u_rms=0.05)
         with dhit.Box(r.n, r.method, "fp32", 0.01) as b:
-            b.init_velocity_field(synth.dhit_field(r.n, seed=r.seed, k0=4.0, u_rms=0.05))
+            b.init_velocity_field(u)
             b.step(r.steps)
             E, st = b.energy_spectrum(r.n // 2)
         got = sch.results[r.rid]["result"]
+        np.testing.assert_array_equal(got["E"], E)
+        for k in ("K", "eps", "S", "F"):
+            assert got[k] == st[k], (r.rid, k)
+    # oracle checks of served runs: the first of each method and grid size
+    checked = set()
+    for r in trace:
+        if (r.method, r.n) in checked:
+            continue
+        checked.add((r.method, r.n))
+        u = synth.dhit_field(r.n, seed=r.seed, k0=4.0, u_rms=0.05)
         if r.method == "dugks":
-            assert np.abs(got["E"] - E).max() <= 1e-6 * E.max()
-            assert abs(got["K"] / st["K"] - 1) <= 1e-6
+            f = O.dugks_step(O.init_equilibrium(u), nu=0.01, nsteps=r.steps)
         else:
-            assert np.abs(got["E"] - E).max() <= 1e-12 * E.max()
-            assert abs(got["K"] / st["K"] - 1) <= 1e-12
+            f = O.lbe_step(O.init_mrt_equilibrium(u), r.method, 0.01, nsteps=r.steps)
+        _, j, _ = O.moments(f)
+        E_ref, st_ref = O.energy_spectrum(j, 0.01, r.n // 2)
+        got = sch.results[r.rid]["result"]
+        keep = E_ref >= 1e-10 * E_ref.max()
+        keep[0] = False
+        err = float((np.abs(got["E"] - E_ref)[keep] / E_ref[keep]).max())
+        print("served vs oracle: %s n=%d steps=%d shell error %.2e" % (r.method, r.n, r.steps, err), flush=True)
+        assert err <= 1e-4, (r.rid, err)
+        assert abs(got["K"] / st_ref["K"] - 1) <= 1e-5
+    assert len(checked) >= 4
