@@ -392,6 +392,63 @@ def consistent_init(u, drho, method, nu, iters, rho0=1.0, mrt=None):
 # Spectral diagnostics, Sec. III
 # ----------------------------------------------------------------------------
 
+def velocity_gradient(u):
+    """G[a, b] = d_a u_b of a velocity field u[3, n, n, n] by spectral
+    differentiation: the transform of d_a u_b is i kappa_a u_hat_b with
+    kappa = 2 pi k / n, the Nyquist component of each derivative dropped (as
+    for S and F, Sec. III, and the vorticity, Sec. IV.B).
+    Returns G[3, 3, n, n, n]."""
+    u = np.asarray(u, dtype=np.float64)
+    n = u.shape[1]
+    k1 = wavenumbers(n)
+    if n % 2 == 0:
+        k1 = np.where(np.abs(k1) == n // 2, 0.0, k1)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    kap = [2.0 * np.pi / n * kx, 2.0 * np.pi / n * ky, 2.0 * np.pi / n * kz]
+    uh = np.fft.fftn(u, axes=(1, 2, 3))
+    G = np.zeros((3, 3) + u.shape[1:])
+    for a in range(3):
+        for b in range(3):
+            G[a, b] = np.real(np.fft.ifftn(1j * kap[a] * uh[b]))
+    return G
+
+
+def dugks_consistent_init(u, drho=None, nu=None, dt=0.5, rho0=1.0, tau=None):
+    """Consistent initial DUGKS state for a prescribed velocity field
+    (Sec. IV.A: the kinetic schemes start from the density fluctuation and
+    the non-equilibrium part that belong to the initial velocity).
+
+    The distribution is the equilibrium of Sec. II.A plus the first-order
+    Chapman-Enskog non-equilibrium part of the BGK model (the collision
+    Omega = (f^eq - f)/tau of Sec. II.A, tau = nu/RT): to first order in the
+    gradients and lowest order in the velocity,
+        f_i = f^eq_i + f1_i,
+        f1_i = -(tau rho0 / RT) W_i (xi_ia xi_ib - RT delta_ab) d_a u_b,
+    whose second moment is the viscous stress -rho0 nu (d_a u_b + d_b u_a)
+    of a divergence-free field and whose density and momentum are zero.  The
+    DUGKS tracks f~ = f - dt/2 Omega(f) (Sec. II.A), so
+        f~_i = f^eq_i + (1 + dt / (2 tau)) f1_i.
+    The gradient is the spectral one (velocity_gradient).  drho: the
+    density fluctuation (None: 0), e.g. initial_pressure(u).
+    Returns f~[19, n, n, n]."""
+    u = _f64(u)
+    if tau is None:
+        tau = tau_dugks(nu)
+    rt = 1.0 / 3.0
+    f = init_equilibrium(u, drho, rho0)
+    G = velocity_gradient(u)
+    c, w = lattice()
+    for i in range(Q):
+        f1 = np.zeros(u.shape[1:])
+        for a in range(3):
+            for b in range(3):
+                qab = c[i, a] * c[i, b] - (rt if a == b else 0.0)
+                if qab != 0.0:
+                    f1 += qab * G[a, b]
+        f[i] += (1.0 + dt / (2.0 * tau)) * (-(tau * rho0 / rt) * w[i]) * f1
+    return f
+
+
 def wavenumbers(n):
     """Integer wavenumber components in numpy FFT order, -n/2 .. n/2-1."""
     return np.fft.fftfreq(n, d=1.0 / n)
