@@ -24,6 +24,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -88,32 +89,52 @@ def time_steps(boxes, steps, torch):
     return start.elapsed_time(stop)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, nu, u256):
-    """The FP64 CPU oracle on a bounded sample of the workload: one MRT-LBE
-    step of the full n^3 field and one DUGKS step of a 128^3 field of the same
-    recipe (the oracle's DUGKS cost per cell does not depend on the box
-    size).  Returns the combined rate defined like `value`."""
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the
+    workload: one MRT-LBE step and one DUGKS step of the full n^3 field
+    (combined like `value`), plus a per-size table (BGK-LBE, MRT-LBE, DUGKS
+    at 32^3, 64^3 and 128^3 on the same field recipe; steps chosen so that
+    each timing covers at least ~0.2 s)."""
     import oracle
     import synth
-    f = oracle.init_mrt_equilibrium(u256)
-    t0 = time.perf_counter()
-    oracle.lbe_step(f, "mrt", nu)
-    t_lbe = time.perf_counter() - t0
-    del f
-    m = min(n, 128)
-    g = oracle.init_equilibrium(synth.dhit_field(m, seed=1, k0=4, u_rms=0.05))
-    t0 = time.perf_counter()
-    oracle.dugks_step(g, nu=nu)
-    t_dugks = time.perf_counter() - t0
-    r_lbe = n ** 3 / t_lbe / 1e6
-    r_dugks = m ** 3 / t_dugks / 1e6
+
+    def rate(method, field, nsteps):
+        m = field.shape[1]
+        f = oracle.init_mrt_equilibrium(field) if method == "mrt" else oracle.init_equilibrium(field)
+        t0 = time.perf_counter()
+        if method == "dugks":
+            oracle.dugks_step(f, nu=nu, nsteps=nsteps)
+        else:
+            oracle.lbe_step(f, method, nu, nsteps=nsteps)
+        dt = time.perf_counter() - t0
+        return m ** 3 * nsteps / dt / 1e6, dt
+
+    r_lbe, t_lbe = rate("mrt", u256, 1)
+    r_dugks, t_dugks = rate("dugks", u256, 1)
     value = 2.0 / (1.0 / r_lbe + 1.0 / r_dugks)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    table = {}
+    for m, steps in ((32, {"bgk": 20, "mrt": 20, "dugks": 4}), (64, {"bgk": 4, "mrt": 4, "dugks": 1}),
+                     (128, {"bgk": 1, "mrt": 1, "dugks": 1})):
+        field = synth.dhit_field(m, seed=1, k0=4, u_rms=0.05)
+        for method in ("bgk", "mrt", "dugks"):
+            table["%s_%d" % (method, m)] = round(rate(method, field, steps[method])[0], 3)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    cores = int(omp) if omp else (os.cpu_count() or 1)
     return {"value": round(value, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "MRT-LBE: 1 oracle step of the %d^3 field (%.2f s, %.3f MLUPS); DUGKS: 1 oracle step "
-                      "of a %d^3 field of the same recipe (%.2f s, %.4f MLUPS); value = 2/(1/r_lbe + 1/r_dugks)"
-                      % (n, t_lbe, r_lbe, m, t_dugks, r_dugks),
-            "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4)}
+            "sample": "one MRT-LBE step (%.2f s) and one DUGKS step (%.2f s) of the %d^3 field; "
+                      "value = 2/(1/r_lbe + 1/r_dugks); per-size table in mlups_by_size" % (t_lbe, t_dugks, n),
+            "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+            "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4), "mlups_by_size": table}
 
 
 def mesh_costs(torch, dhit, n=256, steps=10, warmup=3):
@@ -201,17 +222,29 @@ def extras(torch, dhit, sections="all"):
         torch.cuda.empty_cache()
     if "serving" in want:
         out["serving"] = srv
-    # precision: FP32 vs FP64 spectra at 256^3, nu = 0.0025 and at 64^3 nu = 0.01
+    # precision: FP32 vs FP64 spectra at 256^3, nu = 0.0025, until the 1e-4 shell error is
+    # first crossed (two more outputs after it) or three turnover times t0 = K0/eps0
+    # (Sec. IV.A), outputs every 1000 LBE time units; and at 64^3, nu = 0.01, over 3 t0
+    # with outputs every 100
     prec = {}
-    for n, nu, steps, every in (((256, 0.0025, 400, 100), (64, 0.01, 800, 100)) if "precision" in want else ()):
+    for n, nu, every in (((256, 0.0025, 1000), (64, 0.01, 100)) if "precision" in want else ()):
+        u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
+        t0 = precision.turnover_time(u, nu)
+        span = int(math.ceil(3.0 * t0 / every)) * every
         for method in ("mrt", "dugks"):
-            print("bench: precision %s %d" % (method, n), file=sys.stderr, flush=True)
-            u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
-            k = steps if method == "mrt" else 2 * steps
-            rep, hz = precision.compare_fp32_fp64(u, method, nu, k, every if method == "mrt" else 2 * every)
-            prec["%s_%d" % (method, n)] = {"steps": k, "horizon_1e-4": hz,
-                                             "outputs": [{kk: (round(vv, 8) if isinstance(vv, float) else vv)
-                                                          for kk, vv in r.items()} for r in rep]}
+            print("bench: precision %s %d (t0 = %.0f, up to %d time units)" % (method, n, t0, span),
+                  file=sys.stderr, flush=True)
+            per = 2 if method == "dugks" else 1
+            tag = "%s_%d" % (method, n)
+            show = lambda r, tag=tag, per=per: print(
+                "bench: precision %s step %d shell err %.2e K err %.2e" % (tag, r["step"], r["max_shell_rel"], r["K_rel"]),
+                file=sys.stderr, flush=True)
+            rep, hz = precision.compare_fp32_fp64(u, method, nu, span * per, every * per, after_horizon=2,
+                                                  progress=show)
+            prec[tag] = {"t0": round(t0, 1), "steps_run": rep[-1]["step"], "span_steps": span * per,
+                         "horizon_1e-4": hz,
+                         "outputs": [{kk: (round(vv, 8) if isinstance(vv, float) else vv)
+                                      for kk, vv in r.items()} for r in rep]}
             torch.cuda.empty_cache()
     if "precision" in want:
         out["precision"] = prec

@@ -167,25 +167,33 @@ int32_t set_mesh(dhit_box *b, const double *widths);
  * upload buffer for the call. */
 int32_t initial_pressure(dhit_box *b, const double *u, double *drho);
 
-/* Consistent initial state of an LBE box for a prescribed velocity field
- * (Sec. IV.A: the kinetic schemes start from the density fluctuation and
- * the non-equilibrium part that belong to the initial velocity, found by
- * iterating the scheme with the velocity held at its initial value).
- * Starts as init_velocity_field(b, u, drho) (drho: host, NULL = 0; the
- * spectral pressure of the velocity is the natural first guess), then runs
- * `iters` passes of: one LBE step of the box's method, then every cell's
- * momentum put back to rho0 u with its density and non-equilibrium part
- * kept (f += E(drho, rho0 u) - E(drho, j), E the state init_velocity_field
- * builds).  On return the velocity is u (to rounding), the density and the
- * non-equilibrium part are the scheme's own, and the step counter and the
- * reduction history are reset.  *residual (host, may be NULL) receives the
- * largest change of drho over the last pass (0 for iters = 0).
- * u: host [3][n^3] doubles, idx = (z*n + y)*n + x.  Synchronous; allocates
- * device work space for the call.  DHIT_EMETHOD on a DUGKS box (with the
- * finite-volume fluxes the held-velocity iteration does not converge; start
- * a DUGKS box from the spectral pressure with init_velocity_field),
- * DHIT_EINVAL for a null u or iters < 0, DHIT_ENONFINITE if the density
- * stopped being finite. */
+/* Consistent initial state for a prescribed velocity field (Sec. IV.A: the
+ * kinetic schemes start from the density fluctuation and the
+ * non-equilibrium part that belong to the initial velocity).
+ * drho: host [n^3] or NULL = 0 (the spectral pressure of the velocity,
+ * initial_pressure, is the natural choice); u: host [3][n^3] doubles,
+ * idx = (z*n + y)*n + x.
+ * LBE boxes: the scheme iterated with the velocity held.  Starts as
+ * init_velocity_field(b, u, drho), then runs `iters` passes of: one LBE
+ * step of the box's method, then every cell's momentum put back to rho0 u
+ * with its density and non-equilibrium part kept (f += E(drho, rho0 u) -
+ * E(drho, j), E the state init_velocity_field builds).  On return the
+ * velocity is u (to rounding) and the density and the non-equilibrium part
+ * are the scheme's own.  *residual (host, may be NULL) receives the largest
+ * change of drho over the last pass (0 for iters = 0).
+ * DUGKS boxes: the held-velocity iteration does not converge for the
+ * finite-volume fluxes, so the non-equilibrium part is the first-order
+ * Chapman-Enskog one of the BGK model (Sec. II.A collision, tau = nu/RT),
+ * f1_q = -(tau rho0/RT) W_q (xi_qa xi_qb - RT delta_ab) d_a u_b, with the
+ * spectral velocity gradient (i kappa_a u_hat_b, Nyquist component
+ * dropped), in the tracked variable: f~ = f^eq(drho, rho0 u) +
+ * (1 + dt/(2 tau)) f1 (f~ = f - dt/2 Omega, Sec. II.A).  `iters` is not
+ * used (it must still be >= 0) and *residual is 0.  The box needs unit
+ * cells (DHIT_EMETHOD after set_mesh).
+ * Both: the step counter and the reduction history are reset.
+ * Synchronous; allocates device work space for the call (and the spectrum
+ * work space, DUGKS).  DHIT_EINVAL for a null u or iters < 0,
+ * DHIT_ENONFINITE if the LBE iteration's density stopped being finite. */
 int32_t init_consistent(dhit_box *b, const double *u, const double *drho, int32_t iters, double *residual);
 
 /* Advance an LBE box by nsteps >= 0 steps of dt = 1: fused pull

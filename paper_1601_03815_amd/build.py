@@ -32,6 +32,10 @@ CXXFLAGS = [
 # instructions per plane in FP32) without saving LDS instructions.
 FILE_FLAGS = {
     "dugks_fused.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-mllvm", "-amdgpu-load-store-vectorizer=false"],
+    # multiply-adds contracted within one expression only, so that every
+    # instantiation of the per-cell update (one cell or a run per thread)
+    # rounds alike and batched boxes equal single boxes bit for bit
+    "lbe.hip": ["-ffp-contract=on"],
 }
 
 

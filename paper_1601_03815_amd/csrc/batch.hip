@@ -36,6 +36,8 @@ struct dhit_batch {
   int grid = 0;
   int chunk = 0;  // DUGKS z-chunk of a work item (0 = per-box default)
   int tile = 32;  // DUGKS column-tile width of the batch's kernel (16 or 32)
+  int max_n = 0;  // largest box side
+  int cells_per_thread = 1;  // LBE: cells a thread updates (the same for every box of the launch)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -113,7 +115,7 @@ void build_table(dhit_batch &bt, int chunk) {
       d.nz_chunk = cz;
       d.items = dhit::fused_dugks_items(b->n, bt.tile, cz, &d.tiles_x, &d.tiles_y);
     } else {
-      d.items = dhit::cell_blocks(b->ncell);
+      d.items = dhit::lbe_items(b->ncell, bt.cells_per_thread);
     }
     d.hist = b->hist;
     d.cur = b->cur;
@@ -148,9 +150,10 @@ void upload_table(dhit_batch &bt) {
 void enqueue_step(dhit_batch &bt, int commit) {
   const int nbox = (int)bt.boxes.size();
   if (bt.method == DHIT_DUGKS)
-    dhit::launch_dugks_batch(bt.stream, bt.precision, bt.tile, bt.d_boxes, nbox, bt.total_items, bt.grid);
+    dhit::launch_dugks_batch(bt.stream, bt.precision, bt.tile, bt.max_n, bt.d_boxes, nbox, bt.total_items, bt.grid);
   else
-    dhit::launch_lbe_batch(bt.stream, bt.method, bt.precision, bt.d_boxes, nbox, bt.total_items, bt.grid);
+    dhit::launch_lbe_batch(bt.stream, bt.method, bt.precision, bt.cells_per_thread, bt.d_boxes, nbox, bt.total_items,
+                           bt.grid);
   dhit::launch_finalize_batch(bt.stream, bt.d_boxes, nbox, commit);
 }
 
@@ -280,6 +283,10 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
     bt->precision = boxes[0]->p.precision;
     bt->stream = boxes[0]->stream;
     bt->tile = dhit::fused_tile_width_of(bt->precision);
+    for (int32_t i = 0; i < nbox; ++i) bt->max_n = std::max(bt->max_n, boxes[i]->n);
+    bt->cells_per_thread = dhit::lbe_cells_per_thread(boxes[0]->n, bt->precision);
+    for (int32_t i = 1; i < nbox; ++i)
+      if (dhit::lbe_cells_per_thread(boxes[i]->n, bt->precision) != bt->cells_per_thread) bt->cells_per_thread = 1;
     if (hipMalloc(&bt->d_boxes, nbox * sizeof(dhit::BatchBox)) != hipSuccess ||
         hipMalloc(&bt->d_trial, nbox * dhit::kNumSums * sizeof(double)) != hipSuccess)
       throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");

@@ -123,9 +123,11 @@ int64_t scratch_bytes_of(const dhit_params &p, int64_t pop_bytes) {
   return (p.method == DHIT_DUGKS && p.variant == DHIT_VARIANT_TWO_PASS) ? pop_bytes : 0;
 }
 
-// The fused DUGKS step's one-box tables (see fused_table_entries).
-int64_t fused_table_bytes(const dhit_params &p) {
-  return (p.method == DHIT_DUGKS && p.variant == DHIT_VARIANT_DEFAULT) ? 2 * (int64_t)sizeof(dhit::BatchBox) : 0;
+// The step's one-box tables of an LBE box or a fused-DUGKS box (the box as
+// a table of one entry for each buffer phase, see lbe_table_entries and
+// fused_table_entries).
+int64_t step_table_bytes(const dhit_params &p) {
+  return (p.method != DHIT_DUGKS || p.variant == DHIT_VARIANT_DEFAULT) ? 2 * (int64_t)sizeof(dhit::BatchBox) : 0;
 }
 
 // Blocks (and so partial-sum slots) of the largest per-step launch.
@@ -158,7 +160,7 @@ void require_box(const dhit_box *b) {
 // device address comes from hipGetSymbolAddress, taken once per device with
 // that device current and kept in g_scratch_ptr.
 constexpr int64_t kNoallocPartials = 131072;                      // block partial slots
-constexpr int64_t kNoallocTable = 5 * kNoallocPartials + 8;        // offset of the fused-step tables
+constexpr int64_t kNoallocTable = 5 * kNoallocPartials + 8;        // offset of the step tables
 constexpr int64_t kNoallocDoubles = kNoallocTable + (2 * sizeof(dhit::BatchBox) + 7) / 8;
 static __device__ __align__(256) double scratch[kNoallocDoubles];
 
@@ -231,7 +233,7 @@ int64_t box_bytes(const dhit_params *p) {
   int64_t pop = population_buffer_bytes(p);
   if (pop < 0) return pop;
   return 2 * pop + reduction_blocks(*p) * 5 * 8 + dhit::kHistoryCap * 5 * 8 + scratch_bytes_of(*p, pop) +
-         fused_table_bytes(*p);
+         step_table_bytes(*p);
 }
 
 int32_t create_box(const dhit_params *pp, dhit_box **out) {
@@ -272,13 +274,16 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
           fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
       }
       derive_step_params(*b);
-      if (fused_table_bytes(b->p) > 0) {
-        if (hipMalloc(&b->fused_table, (size_t)fused_table_bytes(b->p)) != hipSuccess)
-          fail(DHIT_ENOMEM, "cannot allocate the fused-step table");
-        b->own_fused_table = true;
+      if (step_table_bytes(b->p) > 0) {
+        if (hipMalloc(&b->step_table, (size_t)step_table_bytes(b->p)) != hipSuccess)
+          fail(DHIT_ENOMEM, "cannot allocate the step table");
+        b->own_step_table = true;
         dhit::BatchBox e[2];
-        dhit::fused_table_entries(*b, e);
-        DHIT_HIP(hipMemcpy(b->fused_table, e, sizeof(e), hipMemcpyHostToDevice));
+        if (b->p.method == DHIT_DUGKS)
+          dhit::fused_table_entries(*b, e);
+        else
+          dhit::lbe_table_entries(*b, e);
+        DHIT_HIP(hipMemcpy(b->step_table, e, sizeof(e), hipMemcpyHostToDevice));
       }
       // zero state until initialised
       DHIT_HIP(hipMemsetAsync(b->f[0], 0, pop, b->stream));
@@ -306,7 +311,7 @@ int32_t destroy_box(dhit_box *b) {
   if (b->hist) (void)hipFree(b->hist);
   if (b->scratch) (void)hipFree(b->scratch);
   if (b->mesh) (void)hipFree(b->mesh);
-  if (b->own_fused_table && b->fused_table) (void)hipFree(b->fused_table);
+  if (b->own_step_table && b->step_table) (void)hipFree(b->step_table);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return DHIT_OK;
@@ -386,9 +391,37 @@ int32_t init_consistent(dhit_box *b, const double *u, const double *drho, int32_
     require_box(b);
     if (!u) fail(DHIT_EINVAL, "null velocity field");
     if (iters < 0) fail(DHIT_EINVAL, "iters must be >= 0");
-    if (b->p.method == DHIT_DUGKS)
-      fail(DHIT_EMETHOD, "init_consistent is defined for LBE boxes; start a DUGKS box with init_velocity_field");
     const size_t bytes = (size_t)b->ncell * sizeof(double);
+    if (b->p.method == DHIT_DUGKS) {
+      // first-order Chapman-Enskog start from the spectral velocity gradient
+      if (b->mesh) fail(DHIT_EMETHOD, "the spectral velocity gradient needs unit cells (this box has a stretched mesh)");
+      double *du = nullptr, *dr = nullptr, *dg = nullptr;
+      auto cleanup = [&]() {
+        (void)hipStreamSynchronize(b->stream);
+        if (du) (void)hipFree(du);
+        if (dr) (void)hipFree(dr);
+        if (dg) (void)hipFree(dg);
+      };
+      try {
+        if (hipMalloc(&du, 3 * bytes) != hipSuccess || hipMalloc(&dg, 9 * bytes) != hipSuccess)
+          fail(DHIT_ENOMEM, "cannot allocate the velocity and gradient buffers");
+        if (drho && hipMalloc(&dr, bytes) != hipSuccess) fail(DHIT_ENOMEM, "cannot allocate upload buffer");
+        DHIT_HIP(hipMemcpyAsync(du, u, 3 * bytes, hipMemcpyHostToDevice, b->stream));
+        if (drho) DHIT_HIP(hipMemcpyAsync(dr, drho, bytes, hipMemcpyHostToDevice, b->stream));
+        dhit::gradient_compute(*b, du, dg);
+        b->cur = 0;
+        dhit::launch_ce_init(*b, du, dr, dg, b->f[0]);
+        DHIT_HIP(hipStreamSynchronize(b->stream));
+      } catch (...) {
+        cleanup();
+        b->steps = 0;
+        throw;
+      }
+      cleanup();
+      if (residual) *residual = 0.0;
+      b->steps = 0;
+      return DHIT_OK;
+    }
     const int blocks = dhit::cell_blocks(b->ncell);
     double *du = nullptr, *dr = nullptr, *dprev = nullptr, *dmax = nullptr;
     auto cleanup = [&]() {
@@ -635,15 +668,17 @@ int32_t step_noalloc(const dhit_params *pp, const void *src, void *dst, double *
     b.max_blocks = (int)kNoallocPartials;
     derive_step_params(b);
     double *out = sums ? sums : ws + 5 * kNoallocPartials;
-    if (p.method == DHIT_DUGKS) {
-      // the fused step reads the box as a table in device memory: written
-      // into the work space by a launch that carries the entries by value
-      dhit::BatchBox e[2];
+    // the step reads the box as a table in device memory: written into the
+    // work space by a launch that carries the entries by value
+    dhit::BatchBox e[2];
+    if (p.method == DHIT_DUGKS)
       dhit::fused_table_entries(b, e);
-      b.fused_table = reinterpret_cast<dhit::BatchBox *>(ws + kNoallocTable);
-      dhit::launch_store_table(b.stream, e, b.fused_table);
+    else
+      dhit::lbe_table_entries(b, e);
+    b.step_table = reinterpret_cast<dhit::BatchBox *>(ws + kNoallocTable);
+    dhit::launch_store_table(b.stream, e, b.step_table);
+    if (p.method == DHIT_DUGKS)
       dhit::launch_dugks_step(b, src, dst, out);
-    }
     else
       dhit::launch_lbe_step(b, src, dst, out);
     return DHIT_OK;

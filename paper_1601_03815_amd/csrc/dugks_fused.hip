@@ -80,9 +80,10 @@ enum : int { kR0 = 19, kJx, kJy, kJz, kPxx, kPxy, kPxz, kPyy, kPyz, kPzz };
 // across x/y-faces (three planes).
 constexpr int kNPop = 16, kNQ = 6, kNZ = 4;
 constexpr int kLdsValues = kNPop + 2 * kNQ + 3 * kNZ;  // per column
-// The one-thread march adds the moments of the y-face between each column
-// and the next row (read back by the column above as its lower y-face).
-constexpr int kFusedValues = kLdsValues + 4;
+// The one-thread march adds the ten face-equilibrium terms of the y-face
+// between each column and the next row (read back by the column above as
+// its lower y-face).
+constexpr int kFusedValues = kLdsValues + 10;
 constexpr int pop_index(int id) { return (id >= 1 && id <= 4) ? id - 1 : ((id >= 7 && id <= 18) ? id - 3 : -1); }
 constexpr int q_index(int id) {
   switch (id) {
@@ -314,6 +315,36 @@ __device__ __forceinline__ void face_equilibrium(const Real (&m)[4], const StepP
   });
 }
 
+// Slot of population q among the ten that cross a D-face (increasing q).
+template <int D>
+constexpr int cross_slot(int q) {
+  int k = 0;
+  for (int r = 0; r < q; ++r) k += cdir(r, D) != 0;
+  return k;
+}
+
+// The ten face-equilibrium terms of a D-face, v[cross_slot<D>(q)] =
+// dt beta xi_qD f^eq_q(face) (face_equilibrium), formed once for both of the
+// face's cells.
+template <int D, typename Real>
+__device__ __forceinline__ void face_terms(const Real (&m)[4], const StepParams &p, Real dtbe, Real (&v)[10]) {
+  face_equilibrium<D, Real>(m, p, dtbe, [&](auto q, Real val) { v[cross_slot<D>(q)] = val; });
+}
+
+// acc_q -= S v_q for the face terms of a D-face (S = +1: the centre's upper
+// face, -1: its lower face).
+template <int D, int S, typename Real>
+__device__ __forceinline__ void apply_terms(const Real (&v)[10], Real (&acc)[kQ]) {
+  static_for<kQ>([&](auto q) {
+    if constexpr (cdir(q, D) != 0) {
+      if constexpr (S > 0)
+        acc[q] -= v[cross_slot<D>(q)];
+      else
+        acc[q] += v[cross_slot<D>(q)];
+    }
+  });
+}
+
 // acc_q -= S v_q for the populations crossing a D-face of the centre
 // (S = +1 for its upper face, -1 for its lower face).
 template <int D, int S, typename Real>
@@ -326,14 +357,29 @@ __device__ __forceinline__ void sub_face(const Real (&m)[4], const StepParams &p
   });
 }
 
+// Cell idx of the population array that starts at qbase.  With O32 the
+// byte offset is formed in 32 bits (every population array of the box is
+// below 4 GB), so that the access can go through the array's uniform base
+// in scalar registers with a 32-bit lane offset, with no 64-bit address
+// arithmetic per access.
+template <bool O32, typename T>
+__device__ __forceinline__ T *at_cell(T *qbase, int idx) {
+  if constexpr (O32) {
+    using Byte = std::conditional_t<std::is_const<T>::value, const global_t<char>, global_t<char>>;
+    return reinterpret_cast<T *>(reinterpret_cast<Byte *>(qbase) + (uint32_t)idx * (uint32_t)sizeof(T));
+  } else {
+    return qbase + idx;
+  }
+}
+
 // Issues the loads of the 19 f~ of the column's cell in plane `plane`
 // (periodic in z).
-template <typename Real>
+template <typename Real, bool O32>
 __device__ __forceinline__ void load_raw(const global_t<Real> *__restrict__ ft, int64_t stride, int n, int col, int plane,
                                          Real (&f)[kQ]) {
   const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
-  const global_t<Real> *base = ft + (int64_t)z * n * n;
-  static_for<kQ>([&](auto q) { f[q] = base[(int64_t)q * stride + col]; });
+  const int idx = z * n * n + col;
+  static_for<kQ>([&](auto q) { f[q] = *at_cell<O32>(ft + (int64_t)q * stride, idx); });
 }
 
 // The ten moments drho, j, Pi of a cell (or of the populations get(q)
@@ -429,7 +475,7 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real 
 // The z-march of one tile (bx, by) over the z-chunk bz of a box; adds the
 // moments of the updated cells to v.  L is the block's LDS, kFusedValues
 // values per column: P [kNPop][NT], Q [2][kNQ][NT], Z [3][kNZ][NT].
-template <typename Real, int W>
+template <typename Real, int W, bool O32>
 __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
                                            int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
@@ -473,9 +519,9 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
   // of the column W before, the store and the sums.  Runs after the barrier
   // that ends the iteration which formed the faces.
   auto finish = [&](int plane) {
-    Real ym[4];
-    static_for<4>([&](auto i) { ym[i] = LY[i * NT - W]; });
-    sub_face<1, -1, Real>(ym, p, dtbe, acc_c);
+    Real fym[10];
+    static_for<10>([&](auto k) { fym[k] = LY[k * NT - W]; });
+    apply_terms<1, -1>(fym, acc_c);
     const int cell = plane * n * n + col;
     // plain (L2-allocating) stores: a tile row's 30 updated cells do not
     // fill whole 128-byte lines, and L2 merges them with the neighbouring
@@ -483,12 +529,12 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
     Real res[kQ];
     static_for<kQ>([&](auto q) {
       res[q] = fp_c[q] + acc_c[q];
-      out[(int64_t)q * stride + cell] = res[q];
+      *at_cell<O32>(out + (int64_t)q * stride, cell) = res[q];
     });
     sums_of_populations<Real>(res, p.inv_rho0, v);
   };
 
-  load_raw<Real>(ft, stride, n, col, z0 - 1, pf);
+  load_raw<Real, O32>(ft, stride, n, col, z0 - 1, pf);
   int q2 = 0, q3 = 0;  // Q slot and Z slot of plane p
   // One iteration past the chunk's end only finishes its last centre, so
   // that every centre is completed by the same code (and rounds the same
@@ -577,31 +623,35 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
       using I1 = std::integral_constant<int, 1>;
       using Im1 = std::integral_constant<int, -1>;
       // Each x-face is formed once: every column of an interior row but the
-      // last (the halo column 0 too) forms its x+ face, and a column's x-
-      // face is the x+ face of the column before it, the previous lane (a
-      // tile row is 32 consecutive lanes of one wavefront).  The lane shift
-      // runs with every lane active.
-      Real mxp[4] = {Real(0), Real(0), Real(0), Real(0)}, mxm[4];
+      // last (the halo column 0 too) forms its x+ face and that face's ten
+      // equilibrium terms, and a column's x- terms are the x+ terms of the
+      // column before it, the previous lane (a tile row is 32 consecutive
+      // lanes of one wavefront).  The lane shift runs with every lane active.
+      Real mxp[4] = {Real(0), Real(0), Real(0), Real(0)};
       if (xface) face_moments(I0{}, I0{}, I0{}, mxp);
-      static_for<4>([&](auto i) { mxm[i] = from_previous_lane(mxp[i]); });
+      Real fxp[10], fxm[10];
+      face_terms<0>(mxp, p, dtbe, fxp);
+      static_for<10>([&](auto k) { fxm[k] = from_previous_lane(fxp[k]); });
       // The y-face between the column and the next row is formed once too,
       // by every interior column of every row but the last (halo row 0
-      // too), and left in LY for the column above, which applies it as its
-      // lower face in finish() after the barrier that ends this iteration.
-      Real my[4];
+      // too); its ten terms are left in LY for the column above, which
+      // applies them as its lower face in finish() after the barrier that
+      // ends this iteration.
       if (yface) {
+        Real my[4], fy[10];
         face_moments(I1{}, I0{}, I0{}, my);
-        static_for<4>([&](auto i) { LY[i * NT] = my[i]; });
+        face_terms<1>(my, p, dtbe, fy);
+        static_for<10>([&](auto k) { LY[k * NT] = fy[k]; });
+        if (inner) apply_terms<1, 1>(fy, acc_c);    // y+
       }
       if (inner) {
-        sub_face<0, 1, Real>(mxp, p, dtbe, acc_c);    // x+
-        sub_face<0, -1, Real>(mxm, p, dtbe, acc_c);   // x-
-        sub_face<1, 1, Real>(my, p, dtbe, acc_c);     // y+
+        apply_terms<0, 1>(fxp, acc_c);   // x+
+        apply_terms<0, -1>(fxm, acc_c);  // x-
       }
     }
     phase();
     // loads of the next plane overlap the rest of this one
-    if (p_ < z1) load_raw<Real>(ft, stride, n, col, p_ + 1, pf);
+    if (p_ < z1) load_raw<Real, O32>(ft, stride, n, col, p_ + 1, pf);
 
     if (inner && has_cur) {
       // in-plane terms of the in-plane populations of centre p (the centre
@@ -667,7 +717,7 @@ __device__ __forceinline__ int xcd_tile(int b, int padded) { return (b & 7) * (p
 // [r G, (r+1) G), dealt to the XCDs in contiguous eighths.  A single box is
 // a table of one entry, so a box stepped alone and the same box stepped in
 // a batch run the same machine code and give the same bits.
-template <typename Real, int W>
+template <typename Real, int W, bool O32>
 __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_kernel(const BatchBox *__restrict__ boxes, int nbox,
                                                                   int total_items) {
   __shared__ Real L[kFusedValues * Tile<W>::NT];
@@ -682,7 +732,7 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_
     const int by = (local / d.tiles_x) % d.tiles_y;
     const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
-    fused_tile<Real, W>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp, bx, by, bz,
+    fused_tile<Real, W, O32>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp, bx, by, bz,
                         d.nz_chunk, L, v);
     // the march ends with a barrier: L is free for the block reduction
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
@@ -737,12 +787,12 @@ constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10, k
 constexpr int kSplitValues = kRY + 4;
 
 // Loads of the group's populations of the column's cell in plane `plane`.
-template <typename Real, int G>
+template <typename Real, int G, bool O32>
 __device__ __forceinline__ void load_group(const global_t<Real> *__restrict__ ft, int64_t stride, int n, int col, int plane,
                                            Real (&f)[Group<G>::N]) {
   const int z = plane < 0 ? plane + n : (plane >= n ? plane - n : plane);
-  const global_t<Real> *base = ft + (int64_t)z * n * n;
-  static_for<Group<G>::N>([&](auto i) { f[i] = base[(int64_t)Group<G>::pop(i) * stride + col]; });
+  const int idx = z * n * n + col;
+  static_for<Group<G>::N>([&](auto i) { f[i] = *at_cell<O32>(ft + (int64_t)Group<G>::pop(i) * stride, idx); });
 }
 
 // Partial moment sums over the group's populations (both groups' sets are
@@ -793,7 +843,7 @@ __device__ __forceinline__ void publish_group(const Real (&f)[Group<G>::N], cons
 
 // The z-march of group G of a tile (see above).  L: the block's LDS,
 // kSplitValues values per column.
-template <typename Real, int W, int G>
+template <typename Real, int W, int G, bool O32>
 __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
                                            int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
@@ -832,7 +882,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   static_for<10>([&](auto i) { nxt[i] = Real(0); });
   static_for<4>([&](auto i) { zl[i] = Real(0); });
 
-  load_group<Real, G>(ft, stride, n, col, z0 - 1, pf);
+  load_group<Real, G, O32>(ft, stride, n, col, z0 - 1, pf);
   int q2 = 0, q3 = 0;
   for (int p_ = z0 - 1; p_ <= z1; ++p_) {
     const bool has_prev = p_ > z0;
@@ -986,7 +1036,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
       }
     }
     phase();
-    if (p_ < z1) load_group<Real, G>(ft, stride, n, col, p_ + 1, pf);
+    if (p_ < z1) load_group<Real, G, O32>(ft, stride, n, col, p_ + 1, pf);
     if (p_ >= z0) {
       __syncthreads();
       if (inner) {
@@ -1034,7 +1084,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           double r = 0, ax = 0, ay = 0, az = 0;
           static_for<NG>([&](auto i) {
             constexpr int q = Group<G>::pop(i);
-            out[(int64_t)q * stride + cell] = acc_c[i];  // plain stores, as in fused_tile
+            *at_cell<O32>(out + (int64_t)q * stride, cell) = acc_c[i];  // plain stores, as in fused_tile
             const double x = (double)acc_c[i];
             r += x;
             if constexpr (kCx[q] != 0) ax += kCx[q] * x;
@@ -1067,7 +1117,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
 }
 
 // Work-list kernel of the split march (see dugks_fused_kernel).
-template <typename Real, int W>
+template <typename Real, int W, bool O32>
 __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const BatchBox *__restrict__ boxes, int nbox,
                                                                       int total_items) {
   __shared__ Real L[kSplitValues * Tile<W>::NT];
@@ -1085,9 +1135,9 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const Batc
     const global_t<Real> *src = to_global(static_cast<const Real *>(d.f[d.cur]));
     global_t<Real> *dst = to_global(static_cast<Real *>(d.f[d.cur ^ 1]));
     if (threadIdx.x < Tile<W>::NT)
-      split_tile<Real, W, 0>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
+      split_tile<Real, W, 0, O32>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
     else
-      split_tile<Real, W, 1>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
+      split_tile<Real, W, 1, O32>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
   }
@@ -1143,26 +1193,38 @@ int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tile
 template <typename Real>
 constexpr bool kSplit = sizeof(Real) == 8;
 
-template <typename Real, int W>
+template <typename Real, int W, bool O32>
 static void list_launch(hipStream_t s, const BatchBox *d_boxes, int nbox, int total_items, int grid) {
   grid = (grid + 7) / 8 * 8;  // the XCD numbering of work items needs a multiple of 8
   if constexpr (kSplit<Real>)
-    hipLaunchKernelGGL((fused::dugks_split_kernel<Real, W>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, s, d_boxes,
-                       nbox, total_items);
+    hipLaunchKernelGGL((fused::dugks_split_kernel<Real, W, O32>), dim3(grid), dim3(2 * fused::Tile<W>::NT), 0, s,
+                       d_boxes, nbox, total_items);
   else
-    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes, nbox,
-                       total_items);
+    hipLaunchKernelGGL((fused::dugks_fused_kernel<Real, W, O32>), dim3(grid), dim3(fused::Tile<W>::NT), 0, s, d_boxes,
+                       nbox, total_items);
 }
 
-void launch_dugks_batch(hipStream_t s, int precision, int w, const BatchBox *d_boxes, int nbox, int total_items,
-                        int grid) {
+// Whether 32-bit byte offsets reach every cell of one population array of
+// an n^3 box (n^3 elements of `elem` bytes below 4 GB).
+static bool offsets32(int max_n, int precision) {
+  const uint64_t elem = precision == DHIT_FP64 ? 8 : 4;
+  return (uint64_t)max_n * max_n * max_n * elem < (uint64_t(1) << 32);
+}
+
+void launch_dugks_batch(hipStream_t s, int precision, int w, int max_n, const BatchBox *d_boxes, int nbox,
+                        int total_items, int grid) {
   if (w != 16 && w != 32) throw Error(DHIT_EINVAL, "fused DUGKS tile width must be 16 or 32");
+  const bool o32 = offsets32(max_n, precision);
   if (precision == DHIT_FP64) {
-    if (w == 16) list_launch<double, 16>(s, d_boxes, nbox, total_items, grid);
-    else list_launch<double, 32>(s, d_boxes, nbox, total_items, grid);
+    if (w == 16) o32 ? list_launch<double, 16, true>(s, d_boxes, nbox, total_items, grid)
+                     : list_launch<double, 16, false>(s, d_boxes, nbox, total_items, grid);
+    else o32 ? list_launch<double, 32, true>(s, d_boxes, nbox, total_items, grid)
+             : list_launch<double, 32, false>(s, d_boxes, nbox, total_items, grid);
   } else {
-    if (w == 16) list_launch<float, 16>(s, d_boxes, nbox, total_items, grid);
-    else list_launch<float, 32>(s, d_boxes, nbox, total_items, grid);
+    if (w == 16) o32 ? list_launch<float, 16, true>(s, d_boxes, nbox, total_items, grid)
+                     : list_launch<float, 16, false>(s, d_boxes, nbox, total_items, grid);
+    else o32 ? list_launch<float, 32, true>(s, d_boxes, nbox, total_items, grid)
+             : list_launch<float, 32, false>(s, d_boxes, nbox, total_items, grid);
   }
   DHIT_HIP(hipGetLastError());
 }
@@ -1194,7 +1256,7 @@ void launch_store_table(hipStream_t s, const BatchBox (&e)[2], BatchBox *dst) {
 }
 
 static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out) {
-  if (!b.fused_table) throw Error(DHIT_EINVAL, "box has no fused-step table");
+  if (!b.step_table) throw Error(DHIT_EINVAL, "box has no fused-step table");
   int entry;
   if (src == b.f[0] && dst == b.f[1]) entry = 0;
   else if (src == b.f[1] && dst == b.f[0]) entry = 1;
@@ -1203,7 +1265,7 @@ static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out
   const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
-    launch_dugks_batch(b.stream, b.p.precision, w, b.fused_table + entry, 1, tiles, tiles);
+    launch_dugks_batch(b.stream, b.p.precision, w, b.n, b.step_table + entry, 1, tiles, tiles);
     t.done();
   }
   launch_finalize_sums(b, b.partials, tiles, sums_out);
@@ -1219,14 +1281,14 @@ static int fused_resident_blocks(int precision, int w) {
   hipError_t e;
   if (precision == DHIT_FP64)
     e = w == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 16>), 2 * fused::Tile<16>::NT, 0)
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 16, true>), 2 * fused::Tile<16>::NT, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 32>), 2 * fused::Tile<32>::NT, 0);
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_split_kernel<double, 32, true>), 2 * fused::Tile<32>::NT, 0);
   else
     e = w == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 16>), fused::Tile<16>::NT, 0)
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 16, true>), fused::Tile<16>::NT, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 32>), fused::Tile<32>::NT, 0);
+                      &nb, reinterpret_cast<const void *>(&fused::dugks_fused_kernel<float, 32, true>), fused::Tile<32>::NT, 0);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 

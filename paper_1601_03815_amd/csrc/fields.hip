@@ -23,6 +23,38 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const double *__restrict__
   static_for<kQ>([&](auto q) { f[(int64_t)q * p.stride + cell] = fe[q]; });
 }
 
+// Consistent initial state of a DUGKS box (Sec. IV.A): the equilibrium of
+// Sec. II.A plus the first-order Chapman-Enskog non-equilibrium part of the
+// BGK model, f1_q = -(tau rho0 / RT) W_q (xi_qa xi_qb - RT delta_ab) G_ab
+// with G_ab = d_a u_b, in the tracked variable f~ = f - dt/2 Omega, i.e.
+// f~ = f^eq + (1 + dt/(2 tau)) f1 = f^eq - 3 rho0 (tau + dt/2) W_q
+// (xi_qa xi_qb - delta_ab/3) G_ab.  Evaluated in double, rounded once.
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void ce_init_kernel(const double *__restrict__ u, const double *__restrict__ drho,
+                                                         const double *__restrict__ grad, Real *__restrict__ f,
+                                                         StepParams p, int ncell) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  const double r = drho ? drho[cell] : 0.0;
+  const double jx = p.rho0 * u[cell], jy = p.rho0 * u[(int64_t)ncell + cell], jz = p.rho0 * u[2 * (int64_t)ncell + cell];
+  double G[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) G[a][b] = grad[(int64_t)(3 * a + b) * ncell + cell];
+  double fe[kQ];
+  equilibrium<double>(r, jx, jy, jz, p.rho0, p.inv_rho0, fe);
+  const double coef = -3.0 * p.rho0 * (p.tau + 0.5 * p.dt);
+  static_for<kQ>([&](auto q) {
+    double s = 0.0;
+    static_for<3>([&](auto a) {
+      static_for<3>([&](auto b) {
+        constexpr double qab = double(cdir(q, a) * cdir(q, b)) - (a == b ? 1.0 / 3.0 : 0.0);
+        if constexpr (qab != 0.0) s += qab * G[a][b];
+      });
+    });
+    f[(int64_t)q * p.stride + cell] = Real(fe[q] + coef * kWeight(q) * s);
+  });
+}
+
 // One pass of the initial-state iteration of an LBE box (Sec. IV.A: the
 // kinetic schemes start from the density fluctuation and non-equilibrium
 // part that belong to the initial velocity, found by running the scheme
@@ -211,6 +243,17 @@ void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drh
       hipLaunchKernelGGL((init_kernel<float, false>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho,
                          static_cast<float *>(dst), b.sp, (int)b.ncell);
   }
+  DHIT_HIP(hipGetLastError());
+}
+
+void launch_ce_init(dhit_box &b, const double *d_u, const double *d_drho, const double *d_grad, void *dst) {
+  const int blocks = cell_blocks(b.ncell);
+  if (b.p.precision == DHIT_FP64)
+    hipLaunchKernelGGL((ce_init_kernel<double>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho, d_grad,
+                       static_cast<double *>(dst), b.sp, (int)b.ncell);
+  else
+    hipLaunchKernelGGL((ce_init_kernel<float>), dim3(blocks), dim3(kBlock), 0, b.stream, d_u, d_drho, d_grad,
+                       static_cast<float *>(dst), b.sp, (int)b.ncell);
   DHIT_HIP(hipGetLastError());
 }
 

@@ -112,8 +112,8 @@ struct dhit_box {
   int64_t steps = 0;
   void *scratch = nullptr;     // DUGKS two-pass transform field
   double *mesh = nullptr;      // stretched-mesh tables [3][kMeshTables][n] (DUGKS), NULL = unit cells
-  dhit::BatchBox *fused_table = nullptr;  // fused DUGKS step: the box as a one-entry table, per buffer phase [2]
-  bool own_fused_table = false;
+  dhit::BatchBox *step_table = nullptr;  // LBE and fused DUGKS steps: the box as a one-entry table per buffer phase [2]
+  bool own_step_table = false;
   dhit::StepParams sp{};
   dhit::SpectrumWork *spec = nullptr;
   dhit::KernelTimer *timer = nullptr;
@@ -143,13 +143,19 @@ void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, doub
 void timer_free(dhit_box &b);
 void launch_velocity(dhit_box &b, const void *f, double *d_u);   // u = j / rho0, [3][ncell]
 
-// Batched launches (batch.hip drives them)
-void launch_lbe_batch(hipStream_t s, int method, int precision, BatchBox *d_boxes, int nbox, int total_items,
-                      int grid);
+// Batched launches (batch.hip drives them).  LBE: one launch over the work
+// items (runs of kBlock * cells_per_thread cells) of a device table of boxes;
+// cells_per_thread is lbe_cells_per_thread() of every box of the launch, or 1.
+void launch_lbe_batch(hipStream_t s, int method, int precision, int cells_per_thread, const BatchBox *d_boxes,
+                      int nbox, int total_items, int grid);
+int lbe_cells_per_thread(int n, int precision);
+int lbe_items(int64_t ncell, int cells_per_thread);
+void lbe_table_entries(const dhit_box &b, BatchBox (&e)[2]);
 // One launch of the fused DUGKS kernel (tile width w) over the work items
-// of a device table of boxes; a single box is a table of one entry.
-void launch_dugks_batch(hipStream_t s, int precision, int w, const BatchBox *d_boxes, int nbox, int total_items,
-                        int grid);
+// of a device table of boxes (the largest of side max_n); a single box is a
+// table of one entry.
+void launch_dugks_batch(hipStream_t s, int precision, int w, int max_n, const BatchBox *d_boxes, int nbox,
+                        int total_items, int grid);
 // The two one-entry tables of a box (entry c steps from f[c] to f[1 - c]),
 // and a launch that writes two entries given by value to device memory.
 void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]);
@@ -166,6 +172,13 @@ void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host)
 void spectrum_free(dhit_box &b);
 void vorticity_compute(dhit_box &b, double *omega_host);  // omega = curl(j/rho0), host [3][ncell]
 void pressure_compute(dhit_box &b, const double *u_host, double *drho_host);  // drho = 3 p of a host u
+// Spectral velocity gradient of a device field u[3][ncell] into
+// grad[3 a + b][ncell] = d_a u_b (device).
+void gradient_compute(dhit_box &b, const double *d_u, double *d_grad);
+// DUGKS consistent start: f~ = f^eq(drho, rho0 u) + (1 + dt/(2 tau)) f1 with
+// the first-order Chapman-Enskog part f1 of the velocity gradient (device
+// fields: u [3][ncell], drho [ncell] or NULL, grad [9][ncell]).
+void launch_ce_init(dhit_box &b, const double *d_u, const double *d_drho, const double *d_grad, void *dst);
 
 // Event bracket around one kernel launch when timing is enabled:
 //   TimedLaunch t(b, DHIT_K_LBE); hipLaunchKernelGGL(...); t.done();

@@ -153,6 +153,26 @@ __global__ __launch_bounds__(256) void curl_kernel(const hipfftDoubleComplex *__
   out[m] = o;
 }
 
+// Spectrum of the velocity-gradient component d_a u_b, scaled by `scale`:
+// out = scale i kappa_a u_hat_b on the half spectrum, the Nyquist
+// wavenumber of the derivative direction set to zero (as deriv_kernel).
+__global__ __launch_bounds__(256) void gradient_kernel(const hipfftDoubleComplex *__restrict__ uhb,
+                                                       hipfftDoubleComplex *__restrict__ out, int n, int64_t nhalf,
+                                                       int a, double scale) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nhalf) return;
+  const int nxh = n / 2 + 1;
+  const int64_t r = m / nxh;
+  int k = a == 0 ? (int)(m % nxh) : (a == 1 ? signed_k((int)(r % n), n) : signed_k((int)(r / n), n));
+  if ((n % 2 == 0) && (2 * k == n || 2 * k == -n)) k = 0;
+  const double kap = 2.0 * M_PI / n * k * scale;
+  const hipfftDoubleComplex v = uhb[m];
+  hipfftDoubleComplex o;
+  o.x = -kap * v.y;
+  o.y = kap * v.x;
+  out[m] = o;
+}
+
 // Products of velocity components for the pressure source: set 0 gives
 // (u u, v v, w w), set 1 gives (u v, v w, w u), into three fields of out.
 __global__ __launch_bounds__(256) void products_kernel(const double *__restrict__ u, double *__restrict__ out,
@@ -370,6 +390,25 @@ void pressure_compute(dhit_box &b, const double *u_host, double *drho_host) {
     throw;
   }
   (void)hipFree(du);
+}
+
+void gradient_compute(dhit_box &b, const double *d_u, double *d_grad) {
+  ensure_work(b);
+  SpectrumWork &w = *b.spec;
+  const int n = b.n;
+  DHIT_FFT(hipfftSetStream(w.fwd, b.stream));
+  DHIT_FFT(hipfftSetStream(w.inv, b.stream));
+  DHIT_HIP(hipMemcpyAsync(w.u, d_u, 3 * b.ncell * sizeof(double), hipMemcpyDeviceToDevice, b.stream));
+  DHIT_FFT(hipfftExecD2Z(w.fwd, w.u, w.uh));
+  const double inv_n3 = 1.0 / ((double)n * n * n);  // both transforms are unnormalised
+  const int blocks = (int)((w.nhalf + 255) / 256);
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) {
+      hipLaunchKernelGGL(gradient_kernel, dim3(blocks), dim3(256), 0, b.stream, w.uh + (int64_t)c * w.nhalf, w.tmp, n,
+                         w.nhalf, a, inv_n3);
+      DHIT_HIP(hipGetLastError());
+      DHIT_FFT(hipfftExecZ2D(w.inv, w.tmp, d_grad + (int64_t)(3 * a + c) * b.ncell));
+    }
 }
 
 void vorticity_compute(dhit_box &b, double *omega_host) {

@@ -24,9 +24,25 @@ def resolved_shells(n, nu, eps):
     return max(1, min(n // 2, int(math.floor(n / (2 * math.pi * eta)))))
 
 
-def compare_fp32_fp64(u, method, nu, steps, every, threshold=1e-4, stream=None):
+def turnover_time(u, nu, stream=None):
+    """Large-eddy turnover time t0 = K0/eps0 of a velocity field (Sec. IV.A),
+    from the library's spectrum of an FP64 box initialised with it."""
+    n = u.shape[1]
+    b = Box(n, "mrt", "fp64", nu, stream=stream)
+    try:
+        b.init_velocity_field(u)
+        _, st = b.energy_spectrum(n // 2)
+    finally:
+        b.close()
+    return st["K"] / st["eps"]
+
+
+def compare_fp32_fp64(u, method, nu, steps, every, threshold=1e-4, stream=None, after_horizon=None,
+                      progress=None):
     """Returns a list of outputs (dict per output step) and the horizon
-    (first step whose max relative shell error exceeds `threshold`, or None)."""
+    (first step whose max relative shell error exceeds `threshold`, or None).
+    With `after_horizon` = m the run stops m outputs after the horizon;
+    `progress(rec)` is called at every output."""
     n = u.shape[1]
     b64 = Box(n, method, "fp64", nu, stream=stream)
     b32 = Box(n, method, "fp32", nu, stream=stream)
@@ -46,9 +62,13 @@ def compare_fp32_fp64(u, method, nu, steps, every, threshold=1e-4, stream=None):
                        K_rel=float(abs(s32["K"] / s64["K"] - 1)), eps_rel=float(abs(s32["eps"] / s64["eps"] - 1)),
                        S64=float(s64["S"]), S32=float(s32["S"]))
             out.append(rec)
+            if progress is not None:
+                progress(rec)
             if horizon is None and rec["max_shell_rel"] > threshold:
                 horizon = done
             if done >= steps:
+                break
+            if horizon is not None and after_horizon is not None and done >= horizon + after_horizon * every:
                 break
             k = min(every, steps - done)
             b64.step(k)

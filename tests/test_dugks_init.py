@@ -119,3 +119,45 @@ def test_start_is_the_schemes_slaved_state(nu):
     assert abs(eq[0]) <= 1e-12 and abs(eq[1] - 1) > 0.2, eq
     if tau < dt / 4:
         assert np.all(np.abs(eq[1:] - 1) > 0.2), eq
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [5, 8, 16, 32])
+def test_library_start_against_oracle(precision, n):
+    """init_consistent of a DUGKS box (spectral gradient on the box's hipFFT
+    work space, start evaluated in double and rounded once) against the
+    oracle, with the spectral pressure as drho; then one step from it.
+    FP64: the 1e-12 bar; FP32: the rounding of the stored start (6e-8) and
+    the one-step bound."""
+    import paper_1601_03815_amd as dhit
+    nu, dt = 0.01, 0.5
+    u = synth.dhit_field(n, seed=20 + n, k0=2, u_rms=0.05)
+    d0 = O.initial_pressure(u)
+    ref = O.dugks_consistent_init(u, d0, nu=nu, dt=dt)
+    with dhit.Box(n, "dugks", precision, nu) as b:
+        assert b.init_consistent(u, d0) == 0.0
+        got = b.get_populations()
+        b.step(1)
+        got1 = b.get_populations()
+    tol0, tol1 = (1e-12, 1e-12) if precision == "fp64" else (1e-7, 2e-6)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= tol0 * scale
+    if precision == "fp32":
+        ref = got            # the step starts from the rounded start
+    ref1 = O.dugks_step(ref, nu=nu, dt=dt)
+    assert np.abs(got1 - ref1).max() <= tol1 * np.abs(ref1).max()
+
+
+@pytest.mark.gpu
+def test_library_start_full_size_sampled():
+    """At 128^3 (the DHIT configuration's grid), FP64: the library's start
+    against the oracle's on every cell."""
+    import paper_1601_03815_amd as dhit
+    n, nu = 128, 0.005
+    u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
+    ref = O.dugks_consistent_init(u, nu=nu)
+    with dhit.Box(n, "dugks", "fp64", nu) as b:
+        b.init_consistent(u)
+        got = b.get_populations()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
