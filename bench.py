@@ -209,15 +209,27 @@ def extras(torch, dhit, sections="all"):
         torch.cuda.empty_cache()
     if "ensemble" in want:
         out["ensemble"] = ens
-    # serving: bounded trace, FP32, two HBM budgets
+    # serving: bounded Poisson traces of 300 arrivals (grids 32-256, MRT-LBE or DUGKS,
+    # 500-2000 steps, FP32): 20 requests/s (offered load above the device's capacity)
+    # and 5 requests/s (a stable queue) with the whole HBM as budget, and 20/s with
+    # a 16 GB budget (admission waits); progress printed every 25 results
     srv = {}
-    for label, budget, count in ((("full_hbm", 250e9, 40), ("budget_16GB", 16e9, 40)) if "serving" in want else ()):
+    cases = (("rate20_full_hbm", 20.0, 250e9), ("rate5_full_hbm", 5.0, 250e9), ("rate20_budget_16GB", 20.0, 16e9))
+    for label, rate, budget in (cases if "serving" in want else ()):
         print("bench: serving %s" % label, file=sys.stderr, flush=True)
-        trace = serve.poisson_trace(count, 20.0, seed=7)
+        trace = serve.poisson_trace(300, rate, seed=7)
         be = serve.GpuBackend(precision="fp32", nu=0.01)
-        st = serve.Scheduler(be, budget, max_active=64, chunk=64).run(trace)
+        done = [0]
+
+        def report(req, res, label=label, done=done):
+            done[0] += 1
+            if done[0] % 25 == 0:
+                print("bench: serving %s %d results, last latency %.2f s" % (label, done[0], res["latency"]),
+                      file=sys.stderr, flush=True)
+        st = serve.Scheduler(be, budget, max_active=64, chunk=64).run(trace, on_result=report)
         be.close()
-        st["offered_rate_per_s"] = 20.0
+        st["offered_rate_per_s"] = rate
+        st["arrivals"] = len(trace)
         srv[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         torch.cuda.empty_cache()
     if "serving" in want:

@@ -115,6 +115,14 @@ int64_t population_buffer_bytes(const dhit_params *p);
  * and is not included.  Used by schedulers to admit boxes by HBM budget. */
 int64_t box_bytes(const dhit_params *p);
 
+/* Device bytes of a box's spectrum work space (energy_spectrum,
+ * vorticity, initial_pressure, and the DUGKS init_consistent allocate it on
+ * their first call and keep it until destroy_box): its arrays plus the work
+ * areas of its two hipFFT plans, queried from hipFFT for this n (plans made
+ * without allocation).  For schedulers that admit boxes by HBM budget and
+ * take diagnostics before releasing them.  A negative status on error. */
+int64_t spectrum_bytes(const dhit_params *p);
+
 /* Create a box.  Validates *p; on success *out owns the new box. */
 int32_t create_box(const dhit_params *p, dhit_box **out);
 
@@ -287,6 +295,16 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * outlive the batch.  Synchronous (waits for the boxes' pending work). */
 typedef struct dhit_batch dhit_batch;
 int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune, dhit_batch **out);
+
+/* Replace the batch's boxes by boxes[nbox] (same method and precision as
+ * the batch; the rules of create_batch), for callers whose set of runs
+ * changes often (a serving loop): the device tables are rebuilt in place
+ * (they grow when needed and are never shrunk, so a smaller set frees
+ * nothing and waits for nothing), the autotuned tile width and z-chunk are
+ * kept, and the captured graph is captured again on the next batch_step of
+ * eight steps or more.  Boxes no longer in the set may be destroyed after
+ * the call.  Synchronous for boxes on other streams than the batch's. */
+int32_t batch_update(dhit_batch *bt, dhit_box **boxes, int32_t nbox);
 
 /* Advance every box of the batch by nsteps >= 0 steps.  Asynchronous. */
 int32_t batch_step(dhit_batch *bt, int32_t nsteps);

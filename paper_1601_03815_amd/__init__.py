@@ -8,11 +8,11 @@ the library is missing, importing this package raises ImportError.
 """
 from ._binding import (  # noqa: F401
     DUGKS, FP32, FP64, LBE_BGK, LBE_MRT, METHODS, PRECISIONS, VARIANT_DEFAULT, VARIANT_TWO_PASS,
-    DhitError, NonFiniteError, Params, box_bytes, box_synchronize, create_box, current_populations,
+    DhitError, NonFiniteError, Params, box_bytes, spectrum_bytes, box_synchronize, create_box, current_populations,
     default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, set_mesh, last_error,
     moments, vorticity, initial_pressure, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, step_noalloc, KERNEL_NAMES,
-    create_batch, batch_step, batch_info, destroy_batch,
+    create_batch, batch_update, batch_step, batch_info, destroy_batch,
 )
 from . import _binding
 
@@ -171,6 +171,12 @@ class Batch:
 
     def step(self, nsteps=1):
         batch_step(self.handle, nsteps)
+
+    def update(self, boxes):
+        """Replace the batch's boxes (same method and precision), keeping
+        its device tables and tuned settings."""
+        batch_update(self.handle, [b.handle for b in boxes])
+        self.boxes = list(boxes)
 
     def info(self):
         return batch_info(self.handle)

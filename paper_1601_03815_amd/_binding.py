@@ -76,6 +76,7 @@ def _load():
         "default_params": ([i32, i32, i32, ctypes.c_double, P], i32),
         "population_buffer_bytes": ([P], i64),
         "box_bytes": ([P], i64),
+        "spectrum_bytes": ([P], i64),
         "create_box": ([P, ctypes.POINTER(ctypes.c_void_p)], i32),
         "destroy_box": ([box], i32),
         "init_velocity_field": ([box, dp, dp], i32),
@@ -96,6 +97,7 @@ def _load():
         "step_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32], i32),
         "create_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32, ctypes.POINTER(ctypes.c_void_p)], i32),
         "batch_step": ([ctypes.c_void_p, i32], i32),
+        "batch_update": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), i32], i32),
         "batch_info": ([ctypes.c_void_p, dp], i32),
         "destroy_batch": ([ctypes.c_void_p], i32),
         "set_kernel_timing": ([box, i32], i32),
@@ -162,6 +164,10 @@ def population_buffer_bytes(p):
 
 def box_bytes(p):
     return _check(_lib.box_bytes(ctypes.byref(p)))
+
+
+def spectrum_bytes(p):
+    return _check(_lib.spectrum_bytes(ctypes.byref(p)))
 
 
 def create_box(p):
@@ -282,6 +288,10 @@ def create_batch(handles, autotune=True):
     return out
 
 
+def batch_update(bt, handles):
+    _check(_lib.batch_update(bt, _handle_array(handles), len(handles)))
+
+
 def batch_step(bt, nsteps=1):
     _check(_lib.batch_step(bt, int(nsteps)))
 
@@ -326,9 +336,9 @@ def step_noalloc(p, src_ptr, dst_ptr, sums_ptr=None):
 
 
 EXPORTED = [
-    "default_params", "population_buffer_bytes", "box_bytes", "create_box", "destroy_box",
+    "default_params", "population_buffer_bytes", "box_bytes", "spectrum_bytes", "create_box", "destroy_box",
     "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
-    "step_batch", "create_batch", "batch_step", "batch_info", "destroy_batch",
+    "step_batch", "create_batch", "batch_update", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "step_noalloc", "dhit_last_error",
 ]

@@ -32,6 +32,7 @@ struct dhit_batch {
   std::vector<dhit::BatchBox> h_boxes;
   double *d_partials = nullptr;
   double *d_trial = nullptr;
+  size_t cap_boxes = 0, cap_partials = 0;  // capacity of d_boxes/d_trial (boxes) and d_partials (doubles)
   int total_items = 0;
   int grid = 0;
   int chunk = 0;  // DUGKS z-chunk of a work item (0 = per-box default)
@@ -126,10 +127,20 @@ void build_table(dhit_batch &bt, int chunk) {
     bt.h_boxes.push_back(d);
   }
   bt.total_items = item;
-  if (bt.d_partials) (void)hipFree(bt.d_partials);
-  bt.d_partials = nullptr;
-  if (hipMalloc(&bt.d_partials, partial_off * sizeof(double)) != hipSuccess)
-    throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch partial sums");
+  // grow-only: re-forming a batch with no more partials frees nothing
+  // (hipFree would wait for the whole device)
+  if (partial_off > bt.cap_partials) {
+    const size_t cap = std::max(partial_off, 2 * bt.cap_partials);
+    if (bt.d_partials) {
+      DHIT_HIP(hipStreamSynchronize(bt.stream));
+      (void)hipFree(bt.d_partials);
+    }
+    bt.d_partials = nullptr;
+    bt.cap_partials = 0;
+    if (hipMalloc(&bt.d_partials, cap * sizeof(double)) != hipSuccess)
+      throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch partial sums");
+    bt.cap_partials = cap;
+  }
   for (size_t i = 0; i < bt.h_boxes.size(); ++i) {
     bt.h_boxes[i].partials = bt.d_partials + offs[i];
     bt.h_boxes[i].trial = bt.d_trial + dhit::kNumSums * i;
@@ -264,7 +275,7 @@ void destroy(dhit_batch *bt) {
   delete bt;
 }
 
-dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
+void check_boxes(dhit_box **boxes, int32_t nbox) {
   if (!boxes || nbox <= 0) throw dhit::Error(DHIT_EINVAL, "bad batch arguments");
   for (int32_t i = 0; i < nbox; ++i) {
     if (!boxes[i]) throw dhit::Error(DHIT_EINVAL, "null box in batch");
@@ -276,22 +287,45 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
     for (int32_t j = 0; j < i; ++j)
       if (boxes[j] == boxes[i]) throw dhit::Error(DHIT_EINVAL, "a box appears twice in a batch");
   }
+}
+
+// The batch's box set and what depends on it (largest side, LBE cells per
+// thread; the device tables grow as needed and never shrink).  Boxes on
+// other streams than the batch's are waited for.
+void set_boxes(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
+  bt.boxes.assign(boxes, boxes + nbox);
+  bt.max_n = 0;
+  for (int32_t i = 0; i < nbox; ++i) bt.max_n = std::max(bt.max_n, boxes[i]->n);
+  bt.cells_per_thread = dhit::lbe_cells_per_thread(boxes[0]->n, bt.precision);
+  for (int32_t i = 1; i < nbox; ++i)
+    if (dhit::lbe_cells_per_thread(boxes[i]->n, bt.precision) != bt.cells_per_thread) bt.cells_per_thread = 1;
+  if ((size_t)nbox > bt.cap_boxes) {
+    if (bt.d_boxes || bt.d_trial) DHIT_HIP(hipStreamSynchronize(bt.stream));
+    if (bt.d_boxes) (void)hipFree(bt.d_boxes);
+    if (bt.d_trial) (void)hipFree(bt.d_trial);
+    bt.d_boxes = nullptr;
+    bt.d_trial = nullptr;
+    bt.cap_boxes = 0;
+    const size_t cap = std::max((size_t)nbox, (size_t)16);
+    if (hipMalloc(&bt.d_boxes, cap * sizeof(dhit::BatchBox)) != hipSuccess ||
+        hipMalloc(&bt.d_trial, cap * dhit::kNumSums * sizeof(double)) != hipSuccess)
+      throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");
+    bt.cap_boxes = cap;
+  }
+  // pending work of every box must finish before the batch stream uses it
+  for (auto *b : bt.boxes)
+    if (b->stream != bt.stream) DHIT_HIP(hipStreamSynchronize(b->stream));
+}
+
+dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
+  check_boxes(boxes, nbox);
   dhit_batch *bt = new dhit_batch();
   try {
-    bt->boxes.assign(boxes, boxes + nbox);
     bt->method = boxes[0]->p.method;
     bt->precision = boxes[0]->p.precision;
     bt->stream = boxes[0]->stream;
     bt->tile = dhit::fused_tile_width_of(bt->precision);
-    for (int32_t i = 0; i < nbox; ++i) bt->max_n = std::max(bt->max_n, boxes[i]->n);
-    bt->cells_per_thread = dhit::lbe_cells_per_thread(boxes[0]->n, bt->precision);
-    for (int32_t i = 1; i < nbox; ++i)
-      if (dhit::lbe_cells_per_thread(boxes[i]->n, bt->precision) != bt->cells_per_thread) bt->cells_per_thread = 1;
-    if (hipMalloc(&bt->d_boxes, nbox * sizeof(dhit::BatchBox)) != hipSuccess ||
-        hipMalloc(&bt->d_trial, nbox * dhit::kNumSums * sizeof(double)) != hipSuccess)
-      throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");
-    // pending work of every box must finish before the batch stream uses it
-    for (auto *b : bt->boxes) DHIT_HIP(hipStreamSynchronize(b->stream));
+    set_boxes(*bt, boxes, nbox);
     if (tune) {
       autotune(*bt);
     } else {
@@ -303,6 +337,21 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
     throw;
   }
   return bt;
+}
+
+// A new box set for an existing batch (same method and precision): the
+// tables are rebuilt in the batch's device memory, the tuned tile width
+// and z-chunk are kept, and the captured graph is dropped (captured again
+// on the next run of eight steps or more).
+void update_batch(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
+  check_boxes(boxes, nbox);
+  if (boxes[0]->p.method != bt.method || boxes[0]->p.precision != bt.precision)
+    throw dhit::Error(DHIT_EINVAL, "batch_update: the boxes must have the batch's method and precision");
+  drop_graph(bt);
+  set_boxes(bt, boxes, nbox);
+  build_table(bt, bt.chunk);
+  bt.grid = bt.tuned ? std::min(std::max(bt.grid, 1), std::max(1, bt.total_items))
+                     : std::min(8 * cu_count(), std::max(1, bt.total_items));
 }
 
 void run_steps(dhit_batch &bt, int32_t nsteps, bool use_graph) {
@@ -359,6 +408,14 @@ int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune_flag, dhit
   return guarded_batch([&]() -> int32_t {
     if (!out) throw dhit::Error(DHIT_EINVAL, "null output");
     *out = make_batch(boxes, nbox, autotune_flag);
+    return DHIT_OK;
+  });
+}
+
+int32_t batch_update(dhit_batch *bt, dhit_box **boxes, int32_t nbox) {
+  return guarded_batch([&]() -> int32_t {
+    if (!bt) throw dhit::Error(DHIT_EINVAL, "null batch");
+    update_batch(*bt, boxes, nbox);
     return DHIT_OK;
   });
 }

@@ -159,8 +159,10 @@ void require_box(const dhit_box *b) {
 // the process ends.  In host code `scratch` names a host-side stand-in: the
 // device address comes from hipGetSymbolAddress, taken once per device with
 // that device current and kept in g_scratch_ptr.
-constexpr int64_t kNoallocPartials = 131072;                      // block partial slots
-constexpr int64_t kNoallocTable = 5 * kNoallocPartials + 8;        // offset of the step tables
+constexpr int64_t kNoallocPartials = 131072;                                 // block partial slots
+constexpr int64_t kNoallocLevel = 5 * kNoallocPartials;                        // wide finalisation work space
+constexpr int64_t kNoallocDiscard = kNoallocLevel + dhit::kFinalizeDoubles;    // sums nobody asked for
+constexpr int64_t kNoallocTable = kNoallocDiscard + 8;                         // the step tables
 constexpr int64_t kNoallocDoubles = kNoallocTable + (2 * sizeof(dhit::BatchBox) + 7) / 8;
 static __device__ __align__(256) double scratch[kNoallocDoubles];
 
@@ -232,8 +234,20 @@ int64_t population_buffer_bytes(const dhit_params *p) {
 int64_t box_bytes(const dhit_params *p) {
   int64_t pop = population_buffer_bytes(p);
   if (pop < 0) return pop;
-  return 2 * pop + reduction_blocks(*p) * 5 * 8 + dhit::kHistoryCap * 5 * 8 + scratch_bytes_of(*p, pop) +
+  return 2 * pop + (reduction_blocks(*p) * 5 + dhit::kFinalizeDoubles) * 8 + dhit::kHistoryCap * 5 * 8 +
+         scratch_bytes_of(*p, pop) +
          step_table_bytes(*p);
+}
+
+int64_t spectrum_bytes(const dhit_params *p) {
+  int64_t r = 0;
+  int32_t st = guarded([&]() -> int32_t {
+    if (!p) fail(DHIT_EINVAL, "null params");
+    if (p->n < 4 || p->n > 1024) fail(DHIT_EINVAL, "n must be in [4, 1024]");
+    r = dhit::spectrum_work_bytes(p->n);
+    return DHIT_OK;
+  });
+  return st == DHIT_OK ? r : st;
 }
 
 int32_t create_box(const dhit_params *pp, dhit_box **out) {
@@ -266,13 +280,16 @@ int32_t create_box(const dhit_params *pp, dhit_box **out) {
           fail(DHIT_ENOMEM, "cannot allocate population buffers");
       }
       b->max_blocks = (int)reduction_blocks(b->p);
-      if (hipMalloc(&b->partials, (size_t)b->max_blocks * 5 * sizeof(double)) != hipSuccess ||
+      // block partials, then the wide finalisation's level sums and counter
+      if (hipMalloc(&b->partials, ((size_t)b->max_blocks * 5 + dhit::kFinalizeDoubles) * sizeof(double)) != hipSuccess ||
           hipMalloc(&b->hist, (size_t)dhit::kHistoryCap * 5 * sizeof(double)) != hipSuccess)
         fail(DHIT_ENOMEM, "cannot allocate reduction buffers");
       if (scratch_bytes_of(*pp, pop) > 0) {
         if (hipMalloc(&b->scratch, scratch_bytes_of(*pp, pop)) != hipSuccess)
           fail(DHIT_ENOMEM, "cannot allocate DUGKS scratch field");
       }
+      b->reduce_level = b->partials + (size_t)b->max_blocks * 5;
+      DHIT_HIP(hipMemsetAsync(b->reduce_level, 0, dhit::kFinalizeDoubles * sizeof(double), b->stream));
       derive_step_params(*b);
       if (step_table_bytes(b->p) > 0) {
         if (hipMalloc(&b->step_table, (size_t)step_table_bytes(b->p)) != hipSuccess)
@@ -666,8 +683,11 @@ int32_t step_noalloc(const dhit_params *pp, const void *src, void *dst, double *
     b.stream = static_cast<hipStream_t>(p.stream);
     b.partials = ws;
     b.max_blocks = (int)kNoallocPartials;
+    // its counter starts at zero (the array is zero when the library is
+    // loaded) and every launch that uses it leaves it at zero
+    b.reduce_level = ws + kNoallocLevel;
     derive_step_params(b);
-    double *out = sums ? sums : ws + 5 * kNoallocPartials;
+    double *out = sums ? sums : ws + kNoallocDiscard;
     // the step reads the box as a table in device memory: written into the
     // work space by a launch that carries the entries by value
     dhit::BatchBox e[2];

@@ -218,9 +218,53 @@ void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commi
   DHIT_HIP(hipGetLastError());
 }
 
+// The same sums spread over G blocks when there are many partials: block g
+// sums its contiguous slice [g * per, (g + 1) * per) in a fixed order into
+// level[g], and the block that finishes last (an agent-scope counter) adds
+// level[0..G) in order and resets the counter for the next launch.  The
+// result does not depend on which block is last.  level: kFinalizeLevels x 5
+// doubles, then the counter at a fixed place whatever G is (launches of
+// different G share the work space; zero before the first launch).
+__global__ __launch_bounds__(kBlock) void finalize_sums_wide_kernel(const double *__restrict__ partials, int nblocks,
+                                                                    int per, double *__restrict__ level,
+                                                                    double *__restrict__ out) {
+  __shared__ double smem[kWaves][kNumSums];
+  __shared__ int last;
+  const int lo = blockIdx.x * per, hi = min(nblocks, lo + per);
+  double v[kNumSums] = {0, 0, 0, 0, 0};
+  for (int b = lo + (int)threadIdx.x; b < hi; b += kBlock) {
+    static_for<kNumSums>([&](auto i) { v[i] += partials[(int64_t)i * nblocks + b]; });
+  }
+  block_sum5(v, smem);
+  unsigned *counter = reinterpret_cast<unsigned *>(level + kFinalizeLevels * kNumSums);
+  if (threadIdx.x == 0) {
+    static_for<kNumSums>([&](auto i) {
+      __hip_atomic_store(&level[(int64_t)blockIdx.x * kNumSums + i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    });
+    const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x < kNumSums) {
+    double s = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g)
+      s += __hip_atomic_load(&level[(int64_t)g * kNumSums + threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    out[threadIdx.x] = s;
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Partials one block of the wide finalisation sums.
+constexpr int kFinalizePer = 4096;
+
 void launch_finalize_sums(dhit_box &b, const double *partials, int nblocks, double *out) {
   TimedLaunch t(b, DHIT_K_FINALIZE);
-  hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, b.stream, partials, nblocks, out);
+  const int g = (nblocks + kFinalizePer - 1) / kFinalizePer;
+  if (g > 1 && b.reduce_level && g <= kFinalizeLevels)
+    hipLaunchKernelGGL(finalize_sums_wide_kernel, dim3(g), dim3(kBlock), 0, b.stream, partials, nblocks, kFinalizePer,
+                       b.reduce_level, out);
+  else
+    hipLaunchKernelGGL(finalize_sums_kernel, dim3(1), dim3(1024), 0, b.stream, partials, nblocks, out);
   DHIT_HIP(hipGetLastError());
   t.done();
 }

@@ -1,12 +1,13 @@
 // LBE time step: fused pull streaming + collision (Sec. II.B evolution
-// equation; BGK or MRT collision), a run of 16 bytes of each population
-// per thread (2 cells in FP64, 4 in FP32; one cell if n is not a multiple).
+// equation; BGK or MRT collision), two cells of a row per thread in FP64
+// (one 16-byte access per population; one cell if n is odd), one in FP32.
 //
 // Data layout: 19 population arrays of `stride` elements each (SoA), cell
 // index x fastest.  A wavefront covers 64 consecutive runs, so each of the
-// 19 gathers and 19 stores is one contiguous 1 KB access (the pull of a
+// 19 gathers and 19 stores is one contiguous access (the pull of a
 // population moving in +-x is shifted by one element, still one run; the
-// lanes where the run wraps around the periodic row fix one element up).
+// lanes where a two-cell run wraps around the periodic row fix one element
+// up).
 //
 // Phase: the buffer holds post-collision populations.  Thread (cell x)
 // gathers g_q(x) = f*_q(x - xi_q), which is the pre-collision state of the
@@ -19,13 +20,14 @@
 
 namespace dhit {
 
-// Cells a thread updates: with C consecutive cells of a row per thread,
-// each population moves as one 16-byte access per lane (2 cells in FP64,
-// 4 in FP32; the 19-stream pattern reaches more of the HBM bandwidth with
-// 16-byte than with 8- or 4-byte accesses).  Boxes whose n is not a
-// multiple of C run one cell per thread.
+// Cells a thread updates.  FP64: two consecutive cells of a row, so that
+// each population moves as one 16-byte access per lane (measured 0.962
+// against 0.980 ms per 256^3 MRT step with one cell); boxes with odd n run
+// one cell per thread.  FP32: one cell (runs of 2 or 4 cells measured 15%
+// slower: the registers of several cells' collisions cost occupancy that the
+// wider accesses do not win back).
 template <typename Real>
-constexpr int kRunCells = 16 / (int)sizeof(Real);
+constexpr int kRunCells = sizeof(Real) == 8 ? 2 : 1;
 
 template <typename Real, int C>
 struct Run {

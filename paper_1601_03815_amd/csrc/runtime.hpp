@@ -43,6 +43,11 @@ struct StepParams {
 };
 
 constexpr int kHistoryCap = 4096;
+// Blocks of the wide finalisation of the per-step sums at most (each sums
+// 4096 block partials); its work space is kFinalizeLevels * 5 doubles and a
+// counter that must be zero before the first launch.
+constexpr int kFinalizeLevels = 64;
+constexpr int kFinalizeDoubles = kFinalizeLevels * 5 + 8;
 
 // Geometry tables of a stretched DUGKS mesh (set_mesh), laid out
 // [axis][table][n] doubles; for cell i of an axis with widths w:
@@ -107,6 +112,7 @@ struct dhit_box {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double *partials = nullptr;  // [5][max_blocks]
+  double *reduce_level = nullptr;  // work space of the wide finalisation (kFinalizeDoubles), NULL: one block
   int max_blocks = 0;
   double *hist = nullptr;      // [kHistoryCap][5]
   int64_t steps = 0;
@@ -170,6 +176,7 @@ int fused_dugks_items(int n, int w, int chunk, int *tiles_x, int *tiles_y);
 // Spectrum (spectrum.hip)
 void spectrum_compute(dhit_box &b, double *E_host, int kmax, double *stats_host);
 void spectrum_free(dhit_box &b);
+int64_t spectrum_work_bytes(int n);  // arrays + hipFFT work areas of an n^3 box's spectrum work space
 void vorticity_compute(dhit_box &b, double *omega_host);  // omega = curl(j/rho0), host [3][ncell]
 void pressure_compute(dhit_box &b, const double *u_host, double *drho_host);  // drho = 3 p of a host u
 // Spectral velocity gradient of a device field u[3][ncell] into

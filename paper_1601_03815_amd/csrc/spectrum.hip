@@ -272,6 +272,31 @@ static void ensure_work(dhit_box &b) {
   w->have_inv = true;
 }
 
+// Device bytes of the spectrum work space of an n^3 box: the arrays of
+// ensure_work and the work areas of its two hipFFT plans (made here with
+// automatic allocation off, so nothing is allocated).
+int64_t spectrum_work_bytes(int n) {
+  const int64_t ncell = (int64_t)n * n * n, nhalf = (int64_t)n * n * (n / 2 + 1);
+  const int64_t nshell = (int64_t)std::floor(std::sqrt(3.0) * (n / 2 + 1)) + 2;
+  int64_t bytes = 3 * ncell * (int64_t)sizeof(double) + 4 * nhalf * (int64_t)sizeof(hipfftDoubleComplex) +
+                  2 * kShellParts * nshell * (int64_t)sizeof(unsigned long long) + (int64_t)sizeof(int) +
+                  5 * 1024 * (int64_t)sizeof(double) + 15 * (int64_t)sizeof(double);
+  int dims[3] = {n, n, n};
+  for (int dir = 0; dir < 2; ++dir) {
+    hipfftHandle h = 0;
+    DHIT_FFT(hipfftCreate(&h));
+    size_t work = 0;
+    hipfftResult r = hipfftSetAutoAllocation(h, 0);
+    if (r == HIPFFT_SUCCESS)
+      r = dir == 0 ? hipfftMakePlanMany(h, 3, dims, nullptr, 1, (int)ncell, nullptr, 1, (int)nhalf, HIPFFT_D2Z, 3, &work)
+                   : hipfftMakePlanMany(h, 3, dims, nullptr, 1, (int)nhalf, nullptr, 1, (int)ncell, HIPFFT_Z2D, 1, &work);
+    hipfftDestroy(h);
+    if (r != HIPFFT_SUCCESS) throw Error(DHIT_EDEVICE, "hipfftMakePlanMany failed, code " + std::to_string((int)r));
+    bytes += (int64_t)work;
+  }
+  return bytes;
+}
+
 void spectrum_free(dhit_box &b) {
   SpectrumWork *w = b.spec;
   if (!w) return;

@@ -113,35 +113,45 @@ class Scheduler:
         return admitted
 
     def run(self, trace, clock=time.perf_counter, sleep=time.sleep, on_result=None):
+        """Serves `trace`; returns the latency percentiles, the aggregate
+        cell-update rate and the host time spent in each backend call
+        (`host_s`: start, advance, finish, release, idle)."""
         waiting = list(trace)
         heapq.heapify(waiting)
         t0 = clock()
         cells_steps = 0
+        spent = dict(start=0.0, advance=0.0, finish=0.0, release=0.0, idle=0.0)
+
+        def timed(key, fn, *a):
+            t = clock()
+            r = fn(*a)
+            spent[key] += clock() - t
+            return r
         while waiting or self.active:
             now = clock() - t0
             self._prepare(waiting, now)
-            self._admit(waiting, now)
+            timed("start", self._admit, waiting, now)
             if not self.active:
                 if waiting:
-                    sleep(max(0.0, waiting[0].arrival - (clock() - t0)))
+                    timed("idle", sleep, max(0.0, waiting[0].arrival - (clock() - t0)))
                 continue
             k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
             groups = {}
             for a in self.active:
                 groups.setdefault(a.req.method, []).append(a)
             for method, acts in groups.items():
-                self.backend.advance([a.handle for a in acts], k)
+                timed("advance", self.backend.advance, [a.handle for a in acts], k)
             for a in self.active:
                 a.done += k
                 cells_steps += a.req.n ** 3 * k
             finished = [a for a in self.active if a.done >= a.req.steps]
             for a in finished:
-                res = self.backend.finish(a.handle)
+                res = timed("finish", self.backend.finish, a.handle)
                 t_done = clock() - t0
                 self.results[a.req.rid] = dict(result=res, latency=t_done - a.req.arrival,
                                                wait=a.admitted - a.req.arrival, n=a.req.n,
                                                method=a.req.method, steps=a.req.steps)
-                self.backend.release(a.handle)
+                timed("release", self.backend.release, a.handle)
                 self.in_use -= a.bytes
                 if on_result:
                     on_result(a.req, self.results[a.req.rid])
@@ -154,7 +164,7 @@ class Scheduler:
                     p99_s=float(np.percentile(lat, 99)) if len(lat) else math.nan,
                     mean_s=float(lat.mean()) if len(lat) else math.nan,
                     mlups=cells_steps / wall / 1e6 if wall > 0 else math.nan,
-                    peak_bytes=self.peak_in_use)
+                    peak_bytes=self.peak_in_use, host_s={k: round(v, 3) for k, v in spent.items()})
 
 
 class GpuBackend:
@@ -168,16 +178,18 @@ class GpuBackend:
 
         import torch
 
-        from . import Batch, Box, box_bytes, default_params
+        from . import Batch, Box, box_bytes, default_params, spectrum_bytes
         self._torch = torch
         self._Box, self._Batch = Box, Batch
         self._box_bytes, self._default_params = box_bytes, default_params
+        self._spectrum_bytes = spectrum_bytes
+        self._bytes = {}
         self.precision, self.nu, self.k0, self.u_rms = precision, nu, k0, u_rms
         self.streams = {}
         self.batches = {}   # method -> (uids of its boxes, Batch)
         if fields is None:
             import synth
-            fields = lambda req: synth.dhit_field(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
+            fields = lambda req: synth.dhit_field_gpu(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
         self.fields = fields
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=field_workers)
         self._pending = {}   # rid -> future of the initial field
@@ -193,9 +205,12 @@ class GpuBackend:
 
     def bytes_of(self, req):
         p = self._default_params(req.n, req.method, self.precision, self.nu)
-        # the spectrum work space (u, u_hat, derivative spectrum: ~64 n^3 bytes) is
-        # allocated when the run finishes; count it while the run is active
-        return self._box_bytes(p) + 64 * req.n ** 3
+        # the spectrum work space (arrays and hipFFT work areas) is allocated
+        # when the run finishes; count it while the run is active
+        key = (req.n, req.method)
+        if key not in self._bytes:
+            self._bytes[key] = self._box_bytes(p) + self._spectrum_bytes(p)
+        return self._bytes[key]
 
     def start(self, req):
         fut = self._pending.pop(req.rid, None)
@@ -205,15 +220,17 @@ class GpuBackend:
         return b
 
     def advance(self, boxes, nsteps):
-        # a batch lives as long as its set of runs: it is re-formed only when
-        # a run joins or leaves the method's active set
+        # one batch per method for the whole run: when a run joins or leaves
+        # the method's active set, the batch is re-formed in place (its device
+        # tables are kept, nothing is freed)
         key = tuple(b.uid for b in boxes)
         method = boxes[0].method
         cur = self.batches.get(method)
-        if cur is None or cur[0] != key:
-            if cur is not None:
-                cur[1].close()
+        if cur is None:
             self.batches[method] = (key, self._Batch(boxes, autotune=False))
+        elif cur[0] != key:
+            cur[1].update(boxes)
+            self.batches[method] = (key, cur[1])
         self.batches[method][1].step(nsteps)
 
     def finish(self, box):
@@ -221,11 +238,8 @@ class GpuBackend:
         return dict(E=E, **st)
 
     def release(self, box):
-        # a batch that holds this run is closed first (it would hold a freed box)
-        for method, (key, bt) in list(self.batches.items()):
-            if box.uid in key:
-                bt.close()
-                del self.batches[method]
+        # the batch that held this run is re-formed before its next step (its
+        # key no longer matches the active set); it never steps a freed box
         box.close()
 
     def sync(self):

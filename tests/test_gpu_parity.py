@@ -410,6 +410,42 @@ def test_batch_against_oracle(method, precision):
             b.close()
 
 
+@pytest.mark.parametrize("method", ["mrt", "dugks"])
+def test_batch_update_in_place(method):
+    """A batch re-formed in place (batch_update: a box leaves and is
+    destroyed, two join, a larger set than before) keeps stepping every box
+    exactly as the box alone would (bit for bit), also through graph
+    replays after each update."""
+    sizes = {"a": 8, "b": 12, "c": 16, "d": 5, "e": 24}
+    states = {k: synth.random_populations(n, seed=600 + i) for i, (k, n) in enumerate(sizes.items())}
+    boxes = {k: dhit.Box(n, method, "fp32", 0.01) for k, n in sizes.items()}
+    refs = {k: dhit.Box(n, method, "fp32", 0.01) for k, n in sizes.items()}
+    try:
+        for k in sizes:
+            boxes[k].set_populations(states[k])
+            refs[k].set_populations(states[k])
+        bt = dhit.Batch([boxes["a"], boxes["b"], boxes["c"]], autotune=False)
+        bt.step(9)
+        for k in "abc":
+            refs[k].step(9)
+        boxes["b"].close()
+        refs["b"].close()
+        bt.update([boxes["a"], boxes["c"], boxes["d"], boxes["e"]])
+        bt.step(17)
+        for k in "acde":
+            refs[k].step(17)
+        bt.update([boxes["e"]])
+        bt.step(8)
+        refs["e"].step(8)
+        bt.close()
+        for k in "acde":
+            np.testing.assert_array_equal(boxes[k].get_populations(), refs[k].get_populations())
+            assert boxes[k].steps == refs[k].steps
+    finally:
+        for b in list(boxes.values()) + list(refs.values()):
+            b.close()
+
+
 def test_batch_rejects_mixed_boxes():
     a = dhit.Box(8, "bgk", "fp32", 0.01)
     b = dhit.Box(8, "dugks", "fp32", 0.01)
@@ -438,3 +474,39 @@ def test_dugks_tile_and_chunk_settings(precision, tile, chunk):
         got = box.get_populations()
     ref = O.dugks_step(f0, nu=nu, nsteps=2)
     assert rel_err(got, ref) <= (TOL64 if precision == "fp64" else 2 * TOL32)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_wide_reduction_equals_stored_state(precision):
+    """At 192^3 the per-step reduction has more block partials than one
+    block finalises (the wide finalisation runs, several blocks and an
+    agent-scope counter); over three steps (the counter must come back to
+    zero after each) the history sums and moments() equal the FP64 sums of
+    the stored populations, computed here on the host.  FP64: to 1e-13 of
+    sum |f|.  FP32: the LBE step sums the cells' compensated FP32 moments
+    (taken before the collision, which conserves them), so the per-step sums
+    differ from the stored values' by the FP32 rounding of each cell's
+    moments (moments() forms them the same way): within 1e-7 of sum |f|
+    (one rounding of 6e-8 per cell at most, accumulated linearly) and 1e-6
+    of the energy; a block left out would be off by its share of the sum."""
+    n = 192
+    c, _ = O.lattice()
+    f0 = synth.random_populations(n, seed=9, amplitude=0.01)
+    if precision == "fp32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    with dhit.Box(n, "mrt", precision, 0.01) as b:
+        b.set_populations(f0)
+        for _ in range(3):
+            b.step(1)
+            f = b.get_populations()
+            d = f.sum(axis=0)
+            j = np.einsum("qa,q...->a...", c.astype(np.float64), f)
+            ref = np.array([d.sum(), j[0].sum(), j[1].sum(), j[2].sum(), 0.5 * (j * j).sum()])
+            scale = np.abs(f).sum()
+            tol, etol = (1e-13, 1e-12) if precision == "fp64" else (1e-7, 1e-6)
+            hist = b.sums_history(1)[0]
+            mom = b.moments(want_fields=False)[2]
+            for got in (hist, mom):
+                assert np.abs(got[:4] - ref[:4]).max() <= tol * scale
+                assert abs(got[4] / ref[4] - 1) <= etol

@@ -148,7 +148,7 @@ def test_result_is_the_same_alone_and_in_the_mix():
     be.close()
     assert stats["requests"] == len(trace)
     for r in trace:
-        u = synth.dhit_field(r.n, seed=r.seed, k0=4.0, u_rms=0.05)
+        u = synth.dhit_field_gpu(r.n, seed=r.seed, k0=4.0, u_rms=0.05)   # the backend's field recipe
         with dhit.Box(r.n, r.method, "fp32", 0.01) as b:
             b.init_velocity_field(u)
             b.step(r.steps)
@@ -178,3 +178,51 @@ def test_result_is_the_same_alone_and_in_the_mix():
         assert err <= 1e-4, (r.rid, err)
         assert abs(got["K"] / st_ref["K"] - 1) <= 1e-5
     assert len(checked) >= 4
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [32, 128])
+def test_spectrum_bytes_covers_the_work_space(n):
+    """spectrum_bytes (what the serving loop reserves for a run's final
+    spectrum) covers what energy_spectrum actually allocates on the device:
+    the arrays (3 velocity fields, 4 half spectra) and the hipFFT plans'
+    work areas.  Device memory is read with hipMemGetInfo through PyTorch;
+    allocations are rounded up to pages, hence the slack."""
+    import torch
+
+    import paper_1601_03815_amd as dhit
+    import synth
+    p = dhit.default_params(n, "mrt", "fp32", 0.01)
+    need = dhit.spectrum_bytes(p)
+    arrays = 3 * n ** 3 * 8 + 4 * n * n * (n // 2 + 1) * 16
+    assert need >= arrays
+    with dhit.Box(n, "mrt", "fp32", 0.01) as b:
+        b.init_velocity_field(synth.taylor_green(n, 0.05))
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        b.energy_spectrum()
+        torch.cuda.synchronize()
+        used = free0 - torch.cuda.mem_get_info()[0]
+    print("n=%d spectrum_bytes %d, device memory taken %d" % (n, need, used), flush=True)
+    assert used <= need + (64 << 20)
+
+
+@pytest.mark.parametrize("n", [8, 16, 33])
+def test_torch_field_recipe_matches_host_recipe(n):
+    """synth.dhit_field_gpu (the recipe's transforms through PyTorch; run
+    here on the CPU device) gives dhit_field's field to FFT rounding, and the
+    same bits on every call."""
+    import synth
+    ref = synth.dhit_field(n, seed=5, k0=4.0, u_rms=0.05)
+    got = synth.dhit_field_gpu(n, seed=5, k0=4.0, u_rms=0.05, device="cpu")
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    np.testing.assert_array_equal(got, synth.dhit_field_gpu(n, seed=5, k0=4.0, u_rms=0.05, device="cpu"))
+
+
+@pytest.mark.gpu
+def test_torch_field_recipe_on_the_gpu():
+    import synth
+    ref = synth.dhit_field(64, seed=6, k0=4.0, u_rms=0.05)
+    got = synth.dhit_field_gpu(64, seed=6, k0=4.0, u_rms=0.05)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    np.testing.assert_array_equal(got, synth.dhit_field_gpu(64, seed=6, k0=4.0, u_rms=0.05))
