@@ -774,30 +774,17 @@ constexpr int local_of(int q) {
 //   RB [10]: B's partial moments, then the x-face moments [0..8) formed by A;
 //   SA [4]:  A's part of the sums of its last stored cell (read by B in the
 //            next iteration);
-//   RT [10]: the ten equilibrium terms of the y-face between the column and
-//            the next row, formed by B in the third phase and read after the
-//            third barrier by A of the column (its upper face) and by both
-//            threads of the column above (their lower face).
-// RB also holds, after the third phase, the x+ face terms of B's six
-// x-crossing populations, formed by A; B of the column reads them (its
-// upper face) and B of the next column in the row (its lower face).
-// RA and SA of a column are used only by the two threads of that column,
-// so every reuse is separated from the previous reads by a barrier or by
-// program order within one thread.  RB[c] is also read by B of column
-// c + 1, in the same row, hence the same wavefront, whose reads come before
-// the wavefront's next writes in program order.  RT is read by another
-// row's threads, at the end of an iteration, without a barrier before
-// their next partial moments are written: it has slots of its own, next
-// written after the second barrier of the next iteration.
-constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10, kRT = kSA + 4;
-constexpr int kSplitValues = kRT + 10;
-
-// Slots of the face terms a group keeps or passes on: A keeps the x-face
-// terms of its 11..14; RB carries the x+ terms of B's 1, 2, 7..10; B keeps
-// the y+ face terms of its 3, 4, 7..10.
-constexpr int a_xslot(int q) { return q - 11; }
-constexpr int b_xslot(int q) { return q <= 2 ? q - 1 : q - 5; }
-constexpr int b_yslot(int q) { return q <= 4 ? q - 3 : q - 5; }
+//   RY [4]:  the moments of the y-face between the column and the next row,
+//            formed by B in the third phase and read after the third barrier
+//            by both threads of the column above (its lower y-face).
+// RA, RB and SA of a column are used only by the two threads of that
+// column, so every reuse is separated from the previous reads by a barrier
+// or by program order within one thread.  RY is read by another column,
+// at the end of an iteration, without a barrier before that column's next
+// partial moments are written: it has slots of its own, next written after
+// the second barrier of the next iteration.
+constexpr int kRA = kNPop + 2 * kNQ + 3 * kNZ, kRB = kRA + 12, kSA = kRB + 10, kRY = kSA + 4;
+constexpr int kSplitValues = kRY + 4;
 
 // Loads of the group's populations of the column's cell in plane `plane`.
 template <typename Real, int G, bool O32>
@@ -883,7 +870,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
   Real *const RA = L + kRA * NT + c;
   Real *const RB = L + kRB * NT + c;
   Real *const SA = L + kSA * NT + c;
-  Real *const RT = L + kRT * NT + c;
+  Real *const RY = L + kRY * NT + c;
 
   Real pf[NG];            // the group's f~ of the plane being published
   Real acc_c[NG];         // centre p-1
@@ -933,8 +920,7 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
     });
     __syncthreads();
 
-    Real xt[2][4];  // A: the x+ and x- face terms of its 11..14
-    Real yt[6];     // B: the y+ face terms of its 3, 4, 7..10
+    Real fx[2][4];  // the faces this group forms: A x+ and x-, B y+ and y-
     if (inner) {
       if constexpr (G == 0) {
         // diagonal z-moving populations: in-plane differences D = B(+d1) -
@@ -1026,38 +1012,26 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           });
         };
         using I0 = std::integral_constant<int, 0>;
+        using Im1 = std::integral_constant<int, -1>;
         if constexpr (G == 0) {
           // each x-face formed once, as in fused_tile: x+ by every column of
-          // an interior row but the last; its ten equilibrium terms too: A
-          // keeps its own four, passes B's six on through RB, and takes the
-          // x- terms of its four from the previous lane
+          // an interior row but the last, x- from the previous lane
           Real xp[4] = {Real(0), Real(0), Real(0), Real(0)};
           if (xface) face(I0{}, I0{}, xp);
-          Real t[10];
-          face_terms<0>(xp, p, dtbe, t);
-          static_for<kQ>([&](auto q) {
-            if constexpr (cdir(q, 0) != 0) {
-              if constexpr (group_of(q) == 0) {
-                xt[0][a_xslot(q)] = t[cross_slot<0>(q)];
-                xt[1][a_xslot(q)] = from_previous_lane(t[cross_slot<0>(q)]);
-              } else {
-                if (xface) RB[b_xslot(q) * NT] = t[cross_slot<0>(q)];
-              }
-            }
+          static_for<4>([&](auto i) {
+            fx[0][i] = xp[i];
+            fx[1][i] = from_previous_lane(xp[i]);
           });
         } else {
           // y+ faces only, by every interior column of every row but the
-          // last (halo row 0 too), and their ten terms: B keeps its six and
-          // leaves all ten in RT for A and for the row above
+          // last (halo row 0 too); the y- face is read back from the row below
           if (yface) {
-            Real my[4], t[10];
-            face(I0{}, I0{}, my);
-            face_terms<1>(my, p, dtbe, t);
-            static_for<10>([&](auto k) { RT[k * NT] = t[k]; });
-            static_for<kQ>([&](auto q) {
-              if constexpr (cdir(q, 1) != 0 && group_of(q) == 1) yt[b_yslot(q)] = t[cross_slot<1>(q)];
-            });
+            face(I0{}, I0{}, fx[0]);
+            static_for<4>([&](auto i) { RY[i * NT] = fx[0][i]; });
           }
+        }
+        if constexpr (G == 0) {
+          if (inner) static_for<2>([&](auto f) { static_for<4>([&](auto i) { RB[(f * 4 + i) * NT] = fx[f][i]; }); });
         }
       }
     }
@@ -1066,6 +1040,18 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
     if (p_ >= z0) {
       __syncthreads();
       if (inner) {
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        auto put_face = [&](const Real (&fm)[4], auto D, auto S) {
+          face_equilibrium<D, Real>(fm, p, dtbe, [&](auto q, Real val) {
+            if constexpr (group_of(q) == G) {
+              if constexpr (S > 0)
+                acc_c[local_of(q)] -= val;
+              else
+                acc_c[local_of(q)] += val;
+            }
+          });
+        };
         if constexpr (G == 0) {
           // the z-face between p-1 and p: upper face of centre p-1, lower of centre p
           Real zf[4];
@@ -1076,29 +1062,24 @@ __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft
           });
         }
         if (has_prev) {
-          // the equilibrium terms of the four x/y-faces of centre p-1 for
-          // this group's populations (upper face subtracted, lower added)
-          static_for<kQ>([&](auto q) {
-            if constexpr (group_of(q) == G) {
-              constexpr int i = local_of(q);
-              if constexpr (cdir(q, 0) != 0) {
-                if constexpr (G == 0) {
-                  acc_c[i] -= xt[0][a_xslot(q)];
-                  acc_c[i] += xt[1][a_xslot(q)];
-                } else {
-                  acc_c[i] -= RB[b_xslot(q) * NT];
-                  acc_c[i] += RB[b_xslot(q) * NT - 1];
-                }
-              }
-              if constexpr (cdir(q, 1) != 0) {
-                if constexpr (G == 0)
-                  acc_c[i] -= RT[cross_slot<1>(q) * NT];
-                else
-                  acc_c[i] -= yt[b_yslot(q)];
-                acc_c[i] += RT[cross_slot<1>(q) * NT - W];
-              }
-            }
-          });
+          // equilibrium parts of the four x/y-faces of centre p-1 for this
+          // group's populations: its own two faces and the other group's
+          Real fo[2][4];
+          if constexpr (G == 0) {
+            static_for<4>([&](auto i) { fo[0][i] = RY[i * NT]; fo[1][i] = RY[i * NT - W]; });
+          } else {
+            static_for<2>([&](auto f) { static_for<4>([&](auto i) { fo[f][i] = RB[(f * 4 + i) * NT]; }); });
+            static_for<4>([&](auto i) { fx[1][i] = RY[i * NT - W]; });
+          }
+          using Ip = std::integral_constant<int, 1>;
+          using Im = std::integral_constant<int, -1>;
+          if constexpr (G == 0) {
+            put_face(fx[0], I0{}, Ip{}); put_face(fx[1], I0{}, Im{});
+            put_face(fo[0], I1{}, Ip{}); put_face(fo[1], I1{}, Im{});
+          } else {
+            put_face(fo[0], I0{}, Ip{}); put_face(fo[1], I0{}, Im{});
+            put_face(fx[0], I1{}, Ip{}); put_face(fx[1], I1{}, Im{});
+          }
           const int cell = (p_ - 1) * n * n + col;
           double r = 0, ax = 0, ay = 0, az = 0;
           static_for<NG>([&](auto i) {
