@@ -11,7 +11,9 @@ agree element by element for ever.  These tests measure how long they do.
    initial state in lockstep; every `every` steps the populations are
    compared element by element (largest |GPU - oracle| over the largest
    |oracle|).  The horizon is the first comparison above the 1e-12 bar; the
-   first comparison must be within it.
+   first comparison must be within it.  Spans: 1500 MRT-LBE steps and 300
+   DUGKS steps, or DHIT_LONG_MRT_STEPS / DHIT_LONG_DUGKS_STEPS (the whole
+   three-turnover-time run is 6000 MRT-LBE steps).
 
 2. FP32 against the FP64 oracle at 64^3 (the reduced-size check of the
    precision configuration: nu = 0.01, k0 = 4, u' = 0.05, seed 1) over three
@@ -52,7 +54,9 @@ def _rel(got, ref):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
 
 
-@pytest.mark.parametrize("method,every,max_steps", [("mrt", 50, 1500), ("dugks", 25, 300)])
+@pytest.mark.parametrize("method,every,max_steps", [
+    ("mrt", 50, int(os.environ.get("DHIT_LONG_MRT_STEPS", "1500"))),
+    ("dugks", 25, int(os.environ.get("DHIT_LONG_DUGKS_STEPS", "300")))])
 def test_fp64_parity_horizon_128(method, every, max_steps):
     n, nu = 128, 0.005
     u = synth.dhit_field(n, seed=1, k0=4, u_rms=0.05)
