@@ -563,6 +563,10 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
       fp_p[q] = ftq;
       if constexpr (kCz[q] != 0) nxt[zslot(q)] = -(dtal * ((Real(-0.5 * kCz[q]) - h) * bq));
     });
+    // pf is consumed: the next plane's loads overlap the rest of this one
+    // (the split march issues them later, after its face phase: issued here
+    // they made the FP64 step 5% slower)
+    if (p_ < z1) load_raw<Real, O32>(ft, stride, n, col, p_ + 1, pf);
     __syncthreads();
 
     if (inner) {
@@ -649,9 +653,6 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
         apply_terms<0, -1>(fxm, acc_c);  // x-
       }
     }
-    phase();
-    // loads of the next plane overlap the rest of this one
-    if (p_ < z1) load_raw<Real, O32>(ft, stride, n, col, p_ + 1, pf);
 
     if (inner && has_cur) {
       // in-plane terms of the in-plane populations of centre p (the centre
@@ -1156,7 +1157,7 @@ __global__ void store_table_kernel(BatchBox e0, BatchBox e1, BatchBox *__restric
 
 // Default tile: 32 x 8 columns in both precisions (rows of 256 B in FP64).
 // FP64 (split march, 512 threads): 140 KB of LDS, one block per compute
-// unit; FP32 (256 threads): 44 KB of LDS, two blocks per compute unit
+// unit; FP32 (256 threads): 51 KB of LDS, two blocks per compute unit
 // (two waves per SIMD).
 constexpr int fused_tile_width(int) { return 32; }
 
