@@ -7,7 +7,7 @@ of magnitude within a few Kolmogorov times, so the GPU and the oracle cannot
 agree element by element for ever.  These tests measure how long they do.
 
 1. FP64 parity horizon at 128^3 (the 128^3 DHIT configuration: nu = 0.005,
-   k0 = 4, u' = 0.05, seed 1): the GPU machine and the oracle advance the same
+   k0 = 4, u' = 0.05, seed 1): the library's box on the GPU and the oracle advance the same
    initial state in lockstep; every `every` steps the populations are
    compared element by element (largest |GPU - oracle| over the largest
    |oracle|).  The horizon is the first comparison above the 1e-12 bar; the
