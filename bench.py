@@ -18,6 +18,8 @@ Also measured and reported on the same JSON line:
   * `traffic`: HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE
     counters (committed under profiles/), when they were taken on the
     current kernel source;
+  * `mlups_by_size`: one box per method and precision at 32^3, 64^3 and
+    128^3 (the sizes of the oracle's per-size table);
   * `cpu_baseline`: the FP64 CPU oracle timed on this host (rank 0, N = 1).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -134,7 +136,29 @@ def cpu_baseline(n, nu, u256):
             "sample": "one MRT-LBE step (%.2f s) and one DUGKS step (%.2f s) of the %d^3 field; "
                       "value = 2/(1/r_lbe + 1/r_dugks); per-size table in mlups_by_size" % (t_lbe, t_dugks, n),
             "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+            "mlups_per_core": round(value / cores, 4),
             "mlups_lbe_mrt": round(r_lbe, 4), "mlups_dugks": round(r_dugks, 4), "mlups_by_size": table}
+
+
+def gpu_sizes(torch, dhit, nu, steps=100, warmup=10):
+    """GPU MLUPS of one box per method, precision and size (32^3, 64^3,
+    128^3; the sizes of the oracle's per-size table), same field recipe, on
+    one stream; small boxes are launch-bound."""
+    import synth
+    out = {}
+    stream = torch.cuda.Stream()
+    for m in (32, 64, 128):
+        field = synth.dhit_field(m, seed=1, k0=4, u_rms=0.05)
+        for precision in ("fp64", "fp32"):
+            for method in ("bgk", "mrt", "dugks"):
+                b = dhit.Box(m, method, precision, nu, stream=stream)
+                b.init_velocity_field(field)
+                time_steps([b], warmup, torch)
+                ms = time_steps([b], steps, torch)
+                out.setdefault(precision, {})["%s_%d" % (method, m)] = round(m ** 3 * steps / (ms * 1e-3) / 1e6, 1)
+                b.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def mesh_costs(torch, dhit, n=256, steps=10, warmup=3):
@@ -411,6 +435,8 @@ def main():
         line["mlups_fp32"] = {"combined": round(r["mlups"], 1), "lbe_mrt": round(r["mlups_lbe_mrt"], 1),
                               "dugks": round(r["mlups_dugks"], 1),
                               "speedup_vs_fp64": round(r["mlups"] / fp64["mlups"], 3)}
+    print("bench: per-size rates", file=sys.stderr, flush=True)
+    line["mlups_by_size"] = gpu_sizes(torch, dhit, nu)
     if args.extras:
         line["extras"] = extras(torch, dhit, args.extras)
     if not args.no_cpu_baseline:

@@ -13,7 +13,8 @@ agree element by element for ever.  These tests measure how long they do.
    |oracle|).  The horizon is the first comparison above the 1e-12 bar; the
    first comparison must be within it.  Spans: 1500 MRT-LBE steps and 300
    DUGKS steps, or DHIT_LONG_MRT_STEPS / DHIT_LONG_DUGKS_STEPS (the whole
-   three-turnover-time run is 6000 MRT-LBE steps).
+   three-turnover-time run is 6000 MRT-LBE steps); MRT-LBE comparisons every
+   50 steps, or DHIT_LONG_MRT_EVERY.
 
 2. FP32 against the FP64 oracle at 64^3 (the reduced-size check of the
    precision configuration: nu = 0.01, k0 = 4, u' = 0.05, seed 1) over three
@@ -55,7 +56,7 @@ def _rel(got, ref):
 
 
 @pytest.mark.parametrize("method,every,max_steps", [
-    ("mrt", 50, int(os.environ.get("DHIT_LONG_MRT_STEPS", "1500"))),
+    ("mrt", int(os.environ.get("DHIT_LONG_MRT_EVERY", "50")), int(os.environ.get("DHIT_LONG_MRT_STEPS", "1500"))),
     ("dugks", 25, int(os.environ.get("DHIT_LONG_DUGKS_STEPS", "300")))])
 def test_fp64_parity_horizon_128(method, every, max_steps):
     n, nu = 128, 0.005
