@@ -254,6 +254,7 @@ def extras(torch, dhit, sections="all"):
         be.close()
         st["offered_rate_per_s"] = rate
         st["arrivals"] = len(trace)
+        st["boxes_created"] = be.created
         srv[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         torch.cuda.empty_cache()
     if "serving" in want:

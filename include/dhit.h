@@ -137,6 +137,16 @@ int32_t destroy_box(dhit_box *b);
  * Resets the step counter and the reduction history.  Synchronous. */
 int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho);
 
+/* The same initial state from fields already in device memory: u[3][n^3]
+ * and drho[n^3] (NULL = 0) are device pointers (doubles, the layout of
+ * init_velocity_field's host arrays).  Asynchronous: the state is built by
+ * one kernel enqueued on the box's stream and the call returns at once; the
+ * caller keeps u and drho unchanged until that stream has passed the
+ * kernel.  Allocates nothing and waits for nothing, so a scheduler can
+ * start a run while other work is queued on the device.  Resets the step
+ * counter. */
+int32_t init_velocity_field_device(dhit_box *b, const double *u, const double *drho);
+
 /* Stretched mesh for a DUGKS box (the finite-volume scheme's advantage the
  * paper names in Sec. V; the reconstruction of Sec. II.A with the positions
  * of a non-uniform mesh).  widths: host [3][n] doubles, the width of cell i
@@ -290,9 +300,11 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * sizes) and, if the environment variable DHIT_TUNE_CACHE names a file,
  * read from and appended to it (one line per choice: key, grid, chunk,
  * tile).  Without autotuning a DUGKS batch uses tile width 32.  Work is
- * issued on the first box's stream; the boxes' own streams are synchronised
- * before each batch step and made to wait for it afterwards.  The boxes must
- * outlive the batch.  Synchronous (waits for the boxes' pending work). */
+ * issued on the first box's stream (or the one batch_set_stream names); on
+ * the device, each batch step waits for the work queued on the boxes' own
+ * streams before it, and the boxes' streams wait for the step after it (the
+ * host waits for neither).  The boxes must outlive the batch.  With
+ * autotune, synchronous (the trial steps are timed). */
 typedef struct dhit_batch dhit_batch;
 int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune, dhit_batch **out);
 
@@ -303,10 +315,20 @@ int32_t create_batch(dhit_box **boxes, int32_t nbox, int32_t autotune, dhit_batc
  * nothing and waits for nothing), the autotuned tile width and z-chunk are
  * kept, and the captured graph is captured again on the next batch_step of
  * eight steps or more.  Boxes no longer in the set may be destroyed after
- * the call.  Synchronous for boxes on other streams than the batch's. */
+ * the call (destroy_box waits for the device).  Asynchronous. */
 int32_t batch_update(dhit_batch *bt, dhit_box **boxes, int32_t nbox);
 
-/* Advance every box of the batch by nsteps >= 0 steps.  Asynchronous. */
+/* Issue the batch's later work on `stream` (a hipStream_t; NULL = the
+ * null stream) instead of the first box's stream, e.g. one stream per
+ * method in a serving loop whose boxes keep streams of their own (a box's
+ * stream then only orders that box's own work, such as its spectrum, after
+ * the batch steps it took part in).  Waits for the work already issued on
+ * the batch's previous stream. */
+int32_t batch_set_stream(dhit_batch *bt, void *stream);
+
+/* Advance every box of the batch by nsteps >= 0 steps.  Asynchronous: the
+ * table of buffer indices and step counters goes up through one of two
+ * pinned copies, so the call waits at most for the upload two calls back. */
 int32_t batch_step(dhit_batch *bt, int32_t nsteps);
 
 /* info[6] = (persistent grid size, DUGKS z-chunk (0 = per-box default),

@@ -9,10 +9,11 @@ the library is missing, importing this package raises ImportError.
 from ._binding import (  # noqa: F401
     DUGKS, FP32, FP64, LBE_BGK, LBE_MRT, METHODS, PRECISIONS, VARIANT_DEFAULT, VARIANT_TWO_PASS,
     DhitError, NonFiniteError, Params, box_bytes, spectrum_bytes, box_synchronize, create_box, current_populations,
-    default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_consistent, set_mesh, last_error,
+    default_params, destroy_box, energy_spectrum, get_populations, init_velocity_field, init_velocity_field_device,
+    init_consistent, set_mesh, last_error,
     moments, vorticity, initial_pressure, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, step_noalloc, KERNEL_NAMES,
-    create_batch, batch_update, batch_step, batch_info, destroy_batch,
+    create_batch, batch_update, batch_set_stream, batch_step, batch_info, destroy_batch,
 )
 from . import _binding
 
@@ -87,6 +88,26 @@ class Box:
     # verbs ------------------------------------------------------------------
     def init_velocity_field(self, u, drho=None):
         init_velocity_field(self.handle, self.n, u, drho)
+
+    def init_velocity_field_device(self, u, drho=None):
+        """The same initial state from PyTorch device tensors u (3, n, n, n)
+        and drho (n, n, n) of float64, without host copies; enqueued on the
+        box's stream after the work queued on PyTorch's current stream
+        (boxes without a PyTorch stream: the caller has synchronised)."""
+        import torch
+        n = self.n
+        for t, shape in ((u, (3, n, n, n)), (drho, (n, n, n))):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape
+                                  or not t.is_contiguous()):
+                raise ValueError("expected a contiguous float64 CUDA tensor of shape %s" % (shape,))
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream())
+            # the allocator must not hand the fields' memory to other streams
+            # before the box's stream has read them
+            for t in (u, drho):
+                if t is not None:
+                    t.record_stream(self.stream)
+        init_velocity_field_device(self.handle, u.data_ptr(), None if drho is None else drho.data_ptr())
 
     def set_mesh(self, widths=None):
         """DUGKS boxes: cell widths (3, n) per axis of a stretched periodic
@@ -165,9 +186,19 @@ class Batch:
     """Boxes of one method and precision advanced together: persistent
     batched launches, autotuned, replayed from a captured hipGraph."""
 
-    def __init__(self, boxes, autotune=True):
+    def __init__(self, boxes, autotune=True, stream=None):
         self.boxes = list(boxes)
         self.handle = create_batch([b.handle for b in self.boxes], autotune)
+        self.stream = stream
+        if stream is not None:
+            self.set_stream(stream)
+
+    def set_stream(self, stream):
+        """Issue later steps on `stream` (a torch.cuda.Stream) instead of the
+        first box's stream; each box's own stream is still ordered after the
+        steps it takes part in."""
+        batch_set_stream(self.handle, stream.cuda_stream)
+        self.stream = stream
 
     def step(self, nsteps=1):
         batch_step(self.handle, nsteps)

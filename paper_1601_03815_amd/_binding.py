@@ -80,6 +80,7 @@ def _load():
         "create_box": ([P, ctypes.POINTER(ctypes.c_void_p)], i32),
         "destroy_box": ([box], i32),
         "init_velocity_field": ([box, dp, dp], i32),
+        "init_velocity_field_device": ([box, ctypes.c_void_p, ctypes.c_void_p], i32),
         "init_consistent": ([box, dp, dp, i32, dp], i32),
         "set_mesh": ([box, dp], i32),
         "step_lbe": ([box, i32], i32),
@@ -97,6 +98,7 @@ def _load():
         "step_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32], i32),
         "create_batch": ([ctypes.POINTER(ctypes.c_void_p), i32, i32, ctypes.POINTER(ctypes.c_void_p)], i32),
         "batch_step": ([ctypes.c_void_p, i32], i32),
+        "batch_set_stream": ([ctypes.c_void_p, ctypes.c_void_p], i32),
         "batch_update": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), i32], i32),
         "batch_info": ([ctypes.c_void_p, dp], i32),
         "destroy_batch": ([ctypes.c_void_p], i32),
@@ -184,6 +186,13 @@ def init_velocity_field(h, n, u, drho=None):
     u = _f64_in(u, (3, n, n, n))
     d = None if drho is None else _f64_in(drho, (n, n, n))
     _check(_lib.init_velocity_field(h, _ptr(u), _ptr(d)))
+
+
+def init_velocity_field_device(h, u_ptr, drho_ptr=None):
+    """Initial state from device fields: u_ptr, drho_ptr are device addresses
+    of (3, n^3) and (n^3) doubles (drho_ptr None = 0); asynchronous on the
+    box's stream (the caller keeps the fields until the stream has passed)."""
+    _check(_lib.init_velocity_field_device(h, ctypes.c_void_p(u_ptr), ctypes.c_void_p(drho_ptr or 0)))
 
 
 def set_mesh(h, n, widths=None):
@@ -296,6 +305,12 @@ def batch_step(bt, nsteps=1):
     _check(_lib.batch_step(bt, int(nsteps)))
 
 
+def batch_set_stream(bt, stream):
+    """Issue the batch's later work on `stream` (a hipStream_t as an int,
+    or 0 for the null stream)."""
+    _check(_lib.batch_set_stream(bt, ctypes.c_void_p(int(stream) or None)))
+
+
 def batch_info(bt):
     info = np.zeros(6, dtype=np.int64)
     _check(_lib.batch_info(bt, _ptr(info)))
@@ -337,8 +352,8 @@ def step_noalloc(p, src_ptr, dst_ptr, sums_ptr=None):
 
 EXPORTED = [
     "default_params", "population_buffer_bytes", "box_bytes", "spectrum_bytes", "create_box", "destroy_box",
-    "init_velocity_field", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
+    "init_velocity_field", "init_velocity_field_device", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
-    "step_batch", "create_batch", "batch_update", "batch_step", "batch_info", "destroy_batch",
+    "step_batch", "create_batch", "batch_update", "batch_set_stream", "batch_step", "batch_info", "destroy_batch",
     "set_kernel_timing", "read_kernel_timings", "device_copy", "step_noalloc", "dhit_last_error",
 ]

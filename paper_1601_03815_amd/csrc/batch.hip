@@ -43,6 +43,14 @@ struct dhit_batch {
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
   bool tuned = false;
+  // two pinned staging copies of the table: an upload does not wait for the
+  // work queued on the stream, and a copy is rewritten only once the upload
+  // that read it (two uploads back) has been done
+  dhit::BatchBox *stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_done[2] = {nullptr, nullptr};
+  bool stage_used[2] = {false, false};
+  size_t cap_stage = 0;
+  int stage_next = 0;
 };
 
 namespace {
@@ -148,14 +156,49 @@ void build_table(dhit_batch &bt, int chunk) {
   bt.chunk = chunk;
 }
 
-// Uploads the table, refreshing buffer indices and step counters from the boxes.
+void free_stage(dhit_batch &bt) {
+  for (int k = 0; k < 2; ++k) {
+    if (bt.stage_done[k]) {
+      (void)hipEventSynchronize(bt.stage_done[k]);
+      (void)hipEventDestroy(bt.stage_done[k]);
+    }
+    if (bt.stage[k]) (void)hipHostFree(bt.stage[k]);
+    bt.stage[k] = nullptr;
+    bt.stage_done[k] = nullptr;
+    bt.stage_used[k] = false;
+  }
+  bt.cap_stage = 0;
+}
+
+// Uploads the table, refreshing buffer indices and step counters from the
+// boxes, through the pinned staging copies (asynchronous on the batch's
+// stream).
 void upload_table(dhit_batch &bt) {
+  const size_t nbox = bt.h_boxes.size();
   for (size_t i = 0; i < bt.boxes.size(); ++i) {
     bt.h_boxes[i].cur = bt.boxes[i]->cur;
     bt.h_boxes[i].step = bt.boxes[i]->steps;
   }
-  DHIT_HIP(hipMemcpyAsync(bt.d_boxes, bt.h_boxes.data(), bt.h_boxes.size() * sizeof(dhit::BatchBox),
-                          hipMemcpyHostToDevice, bt.stream));
+  if (nbox > bt.cap_stage) {
+    free_stage(bt);
+    const size_t cap = std::max(nbox, (size_t)16);
+    for (int k = 0; k < 2; ++k) {
+      if (hipHostMalloc(reinterpret_cast<void **>(&bt.stage[k]), cap * sizeof(dhit::BatchBox), hipHostMallocDefault) !=
+          hipSuccess) {
+        free_stage(bt);
+        throw dhit::Error(DHIT_ENOMEM, "cannot allocate the batch's pinned table copies");
+      }
+      DHIT_HIP(hipEventCreateWithFlags(&bt.stage_done[k], hipEventDisableTiming));
+    }
+    bt.cap_stage = cap;
+  }
+  const int k = bt.stage_next;
+  bt.stage_next ^= 1;
+  if (bt.stage_used[k]) DHIT_HIP(hipEventSynchronize(bt.stage_done[k]));
+  std::memcpy(bt.stage[k], bt.h_boxes.data(), nbox * sizeof(dhit::BatchBox));
+  DHIT_HIP(hipMemcpyAsync(bt.d_boxes, bt.stage[k], nbox * sizeof(dhit::BatchBox), hipMemcpyHostToDevice, bt.stream));
+  DHIT_HIP(hipEventRecord(bt.stage_done[k], bt.stream));
+  bt.stage_used[k] = true;
 }
 
 void enqueue_step(dhit_batch &bt, int commit) {
@@ -269,6 +312,7 @@ void destroy(dhit_batch *bt) {
   if (!bt) return;
   if (bt->stream) (void)hipStreamSynchronize(bt->stream);
   drop_graph(*bt);
+  free_stage(*bt);
   if (bt->d_boxes) (void)hipFree(bt->d_boxes);
   if (bt->d_partials) (void)hipFree(bt->d_partials);
   if (bt->d_trial) (void)hipFree(bt->d_trial);
@@ -289,9 +333,25 @@ void check_boxes(dhit_box **boxes, int32_t nbox) {
   }
 }
 
+// Later work on the batch's stream waits, on the device, for the work
+// already queued on the boxes' own streams (the host does not wait).
+void wait_for_boxes(dhit_batch &bt) {
+  std::vector<hipStream_t> seen;
+  for (auto *b : bt.boxes) {
+    if (b->stream == bt.stream || std::find(seen.begin(), seen.end(), b->stream) != seen.end()) continue;
+    seen.push_back(b->stream);
+    hipEvent_t e;
+    DHIT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t r = hipEventRecord(e, b->stream);
+    if (r == hipSuccess) r = hipStreamWaitEvent(bt.stream, e, 0);
+    (void)hipEventDestroy(e);
+    DHIT_HIP(r);
+  }
+}
+
 // The batch's box set and what depends on it (largest side, LBE cells per
-// thread; the device tables grow as needed and never shrink).  Boxes on
-// other streams than the batch's are waited for.
+// thread; the device tables grow as needed and never shrink).  The batch's
+// stream is ordered after the work queued on the boxes' streams.
 void set_boxes(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
   bt.boxes.assign(boxes, boxes + nbox);
   bt.max_n = 0;
@@ -312,9 +372,8 @@ void set_boxes(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
       throw dhit::Error(DHIT_ENOMEM, "cannot allocate batch tables");
     bt.cap_boxes = cap;
   }
-  // pending work of every box must finish before the batch stream uses it
-  for (auto *b : bt.boxes)
-    if (b->stream != bt.stream) DHIT_HIP(hipStreamSynchronize(b->stream));
+  // pending work of every box comes before the batch stream uses it
+  wait_for_boxes(bt);
 }
 
 dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
@@ -357,8 +416,7 @@ void update_batch(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
 void run_steps(dhit_batch &bt, int32_t nsteps, bool use_graph) {
   if (nsteps < 0) throw dhit::Error(DHIT_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return;
-  for (auto *b : bt.boxes)
-    if (b->stream != bt.stream) DHIT_HIP(hipStreamSynchronize(b->stream));
+  wait_for_boxes(bt);
   upload_table(bt);
   int32_t left = nsteps;
   if (use_graph && left >= kGraphSteps) {
@@ -416,6 +474,15 @@ int32_t batch_update(dhit_batch *bt, dhit_box **boxes, int32_t nbox) {
   return guarded_batch([&]() -> int32_t {
     if (!bt) throw dhit::Error(DHIT_EINVAL, "null batch");
     update_batch(*bt, boxes, nbox);
+    return DHIT_OK;
+  });
+}
+
+int32_t batch_set_stream(dhit_batch *bt, void *stream) {
+  return guarded_batch([&]() -> int32_t {
+    if (!bt) throw dhit::Error(DHIT_EINVAL, "null batch");
+    DHIT_HIP(hipStreamSynchronize(bt->stream));
+    bt->stream = static_cast<hipStream_t>(stream);
     return DHIT_OK;
   });
 }

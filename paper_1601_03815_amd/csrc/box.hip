@@ -337,6 +337,17 @@ int32_t destroy_box(dhit_box *b) {
   return DHIT_OK;
 }
 
+int32_t init_velocity_field_device(dhit_box *b, const double *u, const double *drho) {
+  return guarded([&]() -> int32_t {
+    require_box(b);
+    if (!u) fail(DHIT_EINVAL, "null velocity field");
+    b->cur = 0;
+    dhit::launch_init_equilibrium(*b, u, drho, b->f[0]);
+    b->steps = 0;
+    return DHIT_OK;
+  });
+}
+
 int32_t init_velocity_field(dhit_box *b, const double *u, const double *drho) {
   return guarded([&]() -> int32_t {
     require_box(b);

@@ -115,7 +115,11 @@ class Scheduler:
     def run(self, trace, clock=time.perf_counter, sleep=time.sleep, on_result=None):
         """Serves `trace`; returns the latency percentiles, the aggregate
         cell-update rate and the host time spent in each backend call
-        (`host_s`: start, advance, finish, release, idle)."""
+        (`host_s`: start, advance, finish, release, idle).
+
+        Runs whose last steps were issued in one round are finished and
+        released in the next, after that round's steps have been issued:
+        the device works on the next chunk while their results are read."""
         waiting = list(trace)
         heapq.heapify(waiting)
         t0 = clock()
@@ -127,25 +131,30 @@ class Scheduler:
             r = fn(*a)
             spent[key] += clock() - t
             return r
-        while waiting or self.active:
+
+        last_issued = []   # runs whose last steps were issued in the previous round
+        while waiting or self.active or last_issued:
             now = clock() - t0
             self._prepare(waiting, now)
             timed("start", self._admit, waiting, now)
-            if not self.active:
+            issued = []
+            if self.active:
+                k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
+                groups = {}
+                for a in self.active:
+                    groups.setdefault(a.req.method, []).append(a)
+                for method, acts in groups.items():
+                    timed("advance", self.backend.advance, [a.handle for a in acts], k)
+                for a in self.active:
+                    a.done += k
+                    cells_steps += a.req.n ** 3 * k
+                issued = [a for a in self.active if a.done >= a.req.steps]
+                self.active = [a for a in self.active if a.done < a.req.steps]
+            elif not last_issued:
                 if waiting:
                     timed("idle", sleep, max(0.0, waiting[0].arrival - (clock() - t0)))
                 continue
-            k = min(self.chunk, min(a.req.steps - a.done for a in self.active))
-            groups = {}
-            for a in self.active:
-                groups.setdefault(a.req.method, []).append(a)
-            for method, acts in groups.items():
-                timed("advance", self.backend.advance, [a.handle for a in acts], k)
-            for a in self.active:
-                a.done += k
-                cells_steps += a.req.n ** 3 * k
-            finished = [a for a in self.active if a.done >= a.req.steps]
-            for a in finished:
+            for a in last_issued:
                 res = timed("finish", self.backend.finish, a.handle)
                 t_done = clock() - t0
                 self.results[a.req.rid] = dict(result=res, latency=t_done - a.req.arrival,
@@ -155,7 +164,7 @@ class Scheduler:
                 self.in_use -= a.bytes
                 if on_result:
                     on_result(a.req, self.results[a.req.rid])
-            self.active = [a for a in self.active if a.done < a.req.steps]
+            last_issued = issued
         self.backend.sync()
         wall = clock() - t0
         lat = np.array([r["latency"] for r in self.results.values()])
@@ -169,11 +178,23 @@ class Scheduler:
 
 class GpuBackend:
     """Runs requests as library boxes on the current GPU: FP32 by default,
-    one PyTorch stream per method, one batch per method and chunk.  Initial
-    fields are generated on host threads from the request's arrival on, so
-    that admission does not wait for them."""
+    one PyTorch stream per method, one batch per method and chunk.
 
-    def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None, field_workers=4):
+    Nothing on the way from admission to release allocates or frees device
+    memory once the sizes in the trace have been seen, so no call waits for
+    the whole device: initial fields are generated on host threads from the
+    request's arrival on, copied to the device on a stream of their own
+    (which does not wait for the steps queued on the methods' streams) and
+    turned into the initial state on the method's stream by
+    `init_velocity_field_device`; a finished run's box goes back to a pool
+    (up to `idle_bytes` of idle boxes, the rest are
+    closed) and the next run of that size and method takes it, spectrum
+    work space and hipFFT plans included.  Idle pooled boxes are device
+    memory outside the scheduler's budget, at most `idle_bytes` of it; a
+    box released beyond that is closed (which waits for the device)."""
+
+    def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None, field_workers=4,
+                 idle_bytes=32e9):
         import concurrent.futures
 
         import torch
@@ -186,13 +207,19 @@ class GpuBackend:
         self._bytes = {}
         self.precision, self.nu, self.k0, self.u_rms = precision, nu, k0, u_rms
         self.streams = {}
-        self.batches = {}   # method -> (uids of its boxes, Batch)
+        self.batches = {}   # method -> (key of its active set, Batch)
+        self.idle_bytes = float(idle_bytes)
+        self._idle = {}     # (n, method) -> idle boxes
+        self._idle_total = 0
+        self._runs = 0      # runs started (tells a reused box's runs apart in batch keys)
+        self.created = 0    # boxes created (the rest of the runs reused a pooled box)
         if fields is None:
             import synth
             fields = lambda req: synth.dhit_field_gpu(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
         self.fields = fields
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=field_workers)
-        self._pending = {}   # rid -> future of the initial field
+        self._pending = {}   # rid -> future of the initial field (host array)
+        self._upload = torch.cuda.Stream()
 
     def prepare(self, req):
         if req.rid not in self._pending:
@@ -213,21 +240,36 @@ class GpuBackend:
         return self._bytes[key]
 
     def start(self, req):
+        torch = self._torch
         fut = self._pending.pop(req.rid, None)
         u = fut.result() if fut is not None else self.fields(req)
-        b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._stream(req.method))
-        b.init_velocity_field(u)
+        idle = self._idle.get((req.n, req.method))
+        if idle:
+            b = idle.pop()
+            self._idle_total -= self.bytes_of(req)
+        else:
+            # each box has a stream of its own: its upload, initial state and
+            # spectrum wait only for the batch steps it takes part in
+            b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._torch.cuda.Stream())
+            self.created += 1
+        with torch.cuda.stream(self._upload):
+            # a copy from pageable memory returns when it is done; the box's
+            # stream then waits for the upload stream, not the reverse
+            ud = torch.from_numpy(u).to("cuda")
+            b.init_velocity_field_device(ud)
+        self._runs += 1
+        b.serve_run = self._runs
         return b
 
     def advance(self, boxes, nsteps):
         # one batch per method for the whole run: when a run joins or leaves
         # the method's active set, the batch is re-formed in place (its device
         # tables are kept, nothing is freed)
-        key = tuple(b.uid for b in boxes)
+        key = tuple((b.uid, b.serve_run) for b in boxes)
         method = boxes[0].method
         cur = self.batches.get(method)
         if cur is None:
-            self.batches[method] = (key, self._Batch(boxes, autotune=False))
+            self.batches[method] = (key, self._Batch(boxes, autotune=False, stream=self._stream(method)))
         elif cur[0] != key:
             cur[1].update(boxes)
             self.batches[method] = (key, cur[1])
@@ -239,13 +281,24 @@ class GpuBackend:
 
     def release(self, box):
         # the batch that held this run is re-formed before its next step (its
-        # key no longer matches the active set); it never steps a freed box
-        box.close()
+        # key no longer matches the active set), so it never steps the box
+        # again for this run
+        need = self._bytes[(box.n, box.method)]
+        if self._idle_total + need <= self.idle_bytes:
+            self._idle.setdefault((box.n, box.method), []).append(box)
+            self._idle_total += need
+        else:
+            box.close()
 
     def sync(self):
         for _, bt in self.batches.values():
             bt.close()
         self.batches = {}
+        for idle in self._idle.values():
+            for b in idle:
+                b.close()
+        self._idle = {}
+        self._idle_total = 0
         self._torch.cuda.synchronize()
 
     def close(self):

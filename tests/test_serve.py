@@ -226,3 +226,92 @@ def test_torch_field_recipe_on_the_gpu():
     got = synth.dhit_field_gpu(64, seed=6, k0=4.0, u_rms=0.05)
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     np.testing.assert_array_equal(got, synth.dhit_field_gpu(64, seed=6, k0=4.0, u_rms=0.05))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["bgk", "mrt", "dugks"])
+def test_device_init_equals_host_init(method, precision):
+    """init_velocity_field_device (fields already on the device, no staging,
+    asynchronous on the box's stream) builds the same state as
+    init_velocity_field, bit for bit, with and without drho, and the boxes
+    step alike."""
+    import torch
+
+    import paper_1601_03815_amd as dhit
+    import synth
+    n = 13
+    u = synth.dhit_field(n, seed=4, k0=2, u_rms=0.05)
+    d = 1e-3 * synth.random_populations(n, seed=9)[0]
+    for drho in (None, d):
+        with dhit.Box(n, method, precision, 0.01) as a, dhit.Box(n, method, precision, 0.01) as b:
+            a.init_velocity_field(u, drho)
+            ud = torch.from_numpy(u).cuda()
+            dd = None if drho is None else torch.from_numpy(drho).cuda()
+            b.init_velocity_field_device(ud, dd)
+            del ud, dd
+            np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+            a.step(3)
+            b.step(3)
+            np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+            assert b.steps == 3
+
+
+@pytest.mark.gpu
+def test_pooled_boxes_give_the_same_result():
+    """At most two runs at a time, so later runs take the boxes of earlier
+    ones from the backend's pool (fewer boxes created than runs): every
+    result equals the same run alone on a fresh box, bit for bit."""
+    import paper_1601_03815_amd as dhit
+    import synth
+    from paper_1601_03815_amd.serve import GpuBackend
+
+    trace = poisson_trace(8, 100.0, seed=21, grids=(8, 12), weights=(1, 1), steps=(20, 40))
+    be = GpuBackend(precision="fp32", nu=0.01)
+    sch = Scheduler(be, 4e9, max_active=2, chunk=8)
+    stats = sch.run(trace)
+    be.close()
+    assert stats["requests"] == len(trace)
+    assert be.created < len(trace), be.created
+    for r in trace:
+        u = synth.dhit_field_gpu(r.n, seed=r.seed, k0=4.0, u_rms=0.05)
+        with dhit.Box(r.n, r.method, "fp32", 0.01) as b:
+            b.init_velocity_field(u)
+            b.step(r.steps)
+            E, st = b.energy_spectrum(r.n // 2)
+        got = sch.results[r.rid]["result"]
+        np.testing.assert_array_equal(got["E"], E)
+        for k in ("K", "eps", "S", "F"):
+            assert got[k] == st[k], (r.rid, k)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["mrt", "dugks"])
+def test_batch_on_a_stream_of_its_own(method):
+    """A batch issued on a third stream (batch_set_stream) while each box
+    keeps its own stream: the boxes' states after 9 steps (one graph replay
+    and one eager step) and their spectra, computed on the boxes' streams
+    right after the batch steps, equal the same boxes stepped alone."""
+    import torch
+
+    import paper_1601_03815_amd as dhit
+    import synth
+    sizes = (8, 12, 16)
+    fields = [synth.dhit_field(n, seed=30 + n, k0=2, u_rms=0.05) for n in sizes]
+    boxes = [dhit.Box(n, method, "fp32", 0.01, stream=torch.cuda.Stream()) for n in sizes]
+    for b, u in zip(boxes, fields):
+        b.init_velocity_field(u)
+    bt = dhit.Batch(boxes, autotune=False, stream=torch.cuda.Stream())
+    bt.step(9)
+    got = [(b.energy_spectrum(), b.get_populations()) for b in boxes]
+    bt.close()
+    for b in boxes:
+        b.close()
+    for (E_st, f), n, u in zip(got, sizes, fields):
+        with dhit.Box(n, method, "fp32", 0.01) as a:
+            a.init_velocity_field(u)
+            a.step(9)
+            E, st = a.energy_spectrum()
+            np.testing.assert_array_equal(f, a.get_populations())
+        np.testing.assert_array_equal(E_st[0], E)
+        assert E_st[1]["K"] == st["K"]
