@@ -281,7 +281,8 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
 /* Batches: many boxes of one method and precision advanced together
  * (an ensemble of independent runs, e.g. of different grid sizes).
  * Each step is one persistent kernel launch over a work list spanning all
- * boxes (LBE: 256-cell runs; DUGKS: tile z-chunks of the fused kernel)
+ * boxes (LBE: runs of 256 cells, or 512 when every box's n is even in FP64,
+ * two cells per thread; DUGKS: tile z-chunks of the fused kernel)
  * followed by one launch that finalises every box's global sums; the
  * per-box buffer index and step counter are kept on the device, so runs of
  * 8 steps are replayed from one captured hipGraph.  Results equal

@@ -315,3 +315,26 @@ def test_batch_on_a_stream_of_its_own(method):
             np.testing.assert_array_equal(f, a.get_populations())
         np.testing.assert_array_equal(E_st[0], E)
         assert E_st[1]["K"] == st["K"]
+
+
+@pytest.mark.gpu
+def test_device_init_and_batch_stream_errors():
+    """Error paths of the two entry points the serving loop uses: a null
+    velocity field, wrong tensor shapes or types, a null batch."""
+    import torch
+
+    import paper_1601_03815_amd as dhit
+    from paper_1601_03815_amd import _binding
+    with dhit.Box(6, "mrt", "fp64", 0.01) as b:
+        with pytest.raises(dhit.DhitError) as e:
+            dhit.init_velocity_field_device(b.handle, 0)
+        assert e.value.code == -1
+        with pytest.raises(ValueError):
+            b.init_velocity_field_device(torch.zeros((3, 6, 6, 5), dtype=torch.float64, device="cuda"))
+        with pytest.raises(ValueError):
+            b.init_velocity_field_device(torch.zeros((3, 6, 6, 6), dtype=torch.float32, device="cuda"))
+        with pytest.raises(ValueError):
+            b.init_velocity_field_device(torch.zeros((3, 6, 6, 6), dtype=torch.float64))
+    with pytest.raises(dhit.DhitError) as e:
+        _binding.batch_set_stream(None, 0)
+    assert e.value.code == -1
