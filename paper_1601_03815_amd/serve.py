@@ -8,9 +8,10 @@ method form one batch (one persistent launch per step for all of them, on
 that method's stream, so the two methods' work overlaps on the device).
 The active set is re-formed whenever a run finishes or is admitted, between
 chunks of steps, so requests that arrive while others are running join
-without waiting for them to finish.  A finished run's energy spectrum and
-statistics are computed on the device, its memory is released, and the
-latency from arrival to result is recorded.
+without waiting for them to finish.  A run's energy spectrum and statistics
+are computed on the device in the round after its last steps were issued
+(while the device works on that round's steps), its memory is released, and
+the latency from arrival to result is recorded.
 
 The scheduler talks to a backend object (GPU: `GpuBackend`; tests use a fake
 one) with these methods:
@@ -21,7 +22,8 @@ one) with these methods:
     start(req) -> handle       allocate and initialise the run
     advance(handles, nsteps)   advance active runs (all of one method) by nsteps
     finish(handle) -> result   final diagnostics of a finished run
-    release(handle)            free the run's device memory
+    release(handle)            release the run's device memory (the GPU
+                               backend keeps the box for a later run)
     sync()                     wait for all queued work
 """
 import heapq
@@ -178,17 +180,19 @@ class Scheduler:
 
 class GpuBackend:
     """Runs requests as library boxes on the current GPU: FP32 by default,
-    one PyTorch stream per method, one batch per method and chunk.
+    one batch per method on a PyTorch stream of that method, and a stream
+    of its own for every box (the batch's steps wait for the box's stream
+    and the box's stream for them, on the device).
 
     Nothing on the way from admission to release allocates or frees device
     memory once the sizes in the trace have been seen, so no call waits for
     the whole device: initial fields are generated on host threads from the
     request's arrival on, copied to the device on a stream of their own
     (which does not wait for the steps queued on the methods' streams) and
-    turned into the initial state on the method's stream by
+    turned into the initial state on the box's stream by
     `init_velocity_field_device`; a finished run's box goes back to a pool
-    (up to `idle_bytes` of idle boxes, the rest are
-    closed) and the next run of that size and method takes it, spectrum
+    (up to `idle_bytes` of idle boxes, the rest are closed) and the next
+    run of that size and method takes it, spectrum
     work space and hipFFT plans included.  Idle pooled boxes are device
     memory outside the scheduler's budget, at most `idle_bytes` of it; a
     box released beyond that is closed (which waits for the device)."""
