@@ -300,7 +300,8 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * process under (method, precision, compute units of the device, grid
  * sizes) and, if the environment variable DHIT_TUNE_CACHE names a file,
  * read from and appended to it (one line per choice: key, grid, chunk,
- * tile).  Without autotuning a DUGKS batch uses tile width 32.  Work is
+ * tile).  Without autotuning a DUGKS batch uses tile width 32 and as many
+ * blocks as the device holds at once (LBE: eight per compute unit).  Work is
  * issued on the first box's stream (or the one batch_set_stream names); on
  * the device, each batch step waits for the work queued on the boxes' own
  * streams before it, and the boxes' streams wait for the step after it (the

@@ -64,6 +64,15 @@ int cu_count() {
   return cus > 0 ? cus : 256;
 }
 
+// Persistent grid of a batch that was not tuned: for DUGKS, the blocks the
+// device holds at once (each block then loops over work items, with no
+// second wave of blocks); for LBE, eight blocks per compute unit.
+int default_grid(const dhit_batch &bt) {
+  const int g = bt.method == DHIT_DUGKS ? cu_count() * dhit::fused_resident_blocks_of(bt.precision, bt.tile)
+                                        : 8 * cu_count();
+  return std::min(g, std::max(1, bt.total_items));
+}
+
 std::mutex g_tune_mu;
 struct TuneChoice {
   int grid, chunk, tile;
@@ -389,7 +398,7 @@ dhit_batch *make_batch(dhit_box **boxes, int32_t nbox, int32_t tune) {
       autotune(*bt);
     } else {
       build_table(*bt, 0);
-      bt->grid = std::min(8 * cu_count(), std::max(1, bt->total_items));
+      bt->grid = default_grid(*bt);
     }
   } catch (...) {
     destroy(bt);
@@ -410,7 +419,7 @@ void update_batch(dhit_batch &bt, dhit_box **boxes, int32_t nbox) {
   set_boxes(bt, boxes, nbox);
   build_table(bt, bt.chunk);
   bt.grid = bt.tuned ? std::min(std::max(bt.grid, 1), std::max(1, bt.total_items))
-                     : std::min(8 * cu_count(), std::max(1, bt.total_items));
+                     : default_grid(bt);
 }
 
 void run_steps(dhit_batch &bt, int32_t nsteps, bool use_graph) {

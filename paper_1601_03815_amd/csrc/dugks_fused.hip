@@ -1295,6 +1295,8 @@ static int fused_resident_blocks(int precision, int w) {
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
+int fused_resident_blocks_of(int precision, int w) { return fused_resident_blocks(precision, w); }
+
 // z-chunk that balances a launch.  Its blocks run in rounds of `slots`
 // (compute units x resident blocks); a block marching c planes costs about
 // c + 2 plane iterations (the two halo planes), so the launch costs about

@@ -168,6 +168,9 @@ void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]);
 void launch_store_table(hipStream_t s, const BatchBox (&e)[2], BatchBox *dst);
 void launch_finalize_batch(hipStream_t s, BatchBox *d_boxes, int nbox, int commit);
 int fused_tile_width_of(int precision);
+// Blocks of the fused DUGKS kernel of this precision and tile width that
+// one compute unit holds at once.
+int fused_resident_blocks_of(int precision, int w);
 int fused_default_chunk(int n);
 int fused_balanced_chunk(int n, int tiles_xy, int slots);
 int fused_auto_chunk(const dhit_params &p);
