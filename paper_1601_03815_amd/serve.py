@@ -16,9 +16,11 @@ the latency from arrival to result is recorded.
 The scheduler talks to a backend object (GPU: `GpuBackend`; tests use a fake
 one) with these methods:
     bytes_of(req) -> int       device bytes the run needs while active
-    prepare(req)               optional: called once when the request arrives,
-                               before admission (the GPU backend starts
-                               generating its initial field in the background)
+    prepare(req)               optional: called once for each arrived request,
+                               in arrival order, before admission (the GPU
+                               backend starts generating its initial field
+                               in the background); returning False declines
+                               for now (asked again in the next round)
     start(req) -> handle       allocate and initialise the run
     advance(handles, nsteps)   advance active runs (all of one method) by nsteps
     finish(handle) -> result   final diagnostics of a finished run
@@ -88,13 +90,19 @@ class Scheduler:
         self._prepared = set()
 
     def _prepare(self, waiting, now):
+        # arrived requests in arrival order; a backend may decline (return
+        # False) to bound what it holds ahead, and is asked again next round
         prep = getattr(self.backend, "prepare", None)
         if prep is None:
             return
-        for req in waiting:
-            if req.arrival <= now and req.rid not in self._prepared:
-                self._prepared.add(req.rid)
-                prep(req)
+        for req in sorted(waiting):
+            if req.arrival > now:
+                break
+            if req.rid in self._prepared:
+                continue
+            if prep(req) is False:
+                break
+            self._prepared.add(req.rid)
 
     def _admit(self, waiting, now):
         admitted = []
@@ -186,9 +194,10 @@ class GpuBackend:
 
     Nothing on the way from admission to release allocates or frees device
     memory once the sizes in the trace have been seen, so no call waits for
-    the whole device: initial fields are generated on host threads from the
-    request's arrival on, copied to the device on a stream of their own
-    (which does not wait for the steps queued on the methods' streams) and
+    the whole device: initial fields are generated on the device by host
+    threads from the request's arrival on (at most `fields_ahead` waiting;
+    fields given as host arrays are copied on a stream of their own, which
+    does not wait for the steps queued on the methods' streams) and
     turned into the initial state on the box's stream by
     `init_velocity_field_device`; a finished run's box goes back to a pool
     (up to `idle_bytes` of idle boxes, the rest are closed) and the next
@@ -198,7 +207,7 @@ class GpuBackend:
     box released beyond that is closed (which waits for the device)."""
 
     def __init__(self, precision="fp32", nu=0.01, k0=4.0, u_rms=0.05, fields=None, field_workers=4,
-                 idle_bytes=32e9):
+                 idle_bytes=32e9, fields_ahead=16):
         import concurrent.futures
 
         import torch
@@ -219,15 +228,21 @@ class GpuBackend:
         self.created = 0    # boxes created (the rest of the runs reused a pooled box)
         if fields is None:
             import synth
-            fields = lambda req: synth.dhit_field_gpu(req.n, seed=req.seed, k0=k0, u_rms=u_rms)
+            fields = lambda req: synth.dhit_field_gpu(req.n, seed=req.seed, k0=k0, u_rms=u_rms, as_tensor=True)
         self.fields = fields
+        self.fields_ahead = int(fields_ahead)
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=field_workers)
         self._pending = {}   # rid -> future of the initial field (host array)
         self._upload = torch.cuda.Stream()
 
     def prepare(self, req):
+        # at most `fields_ahead` fields wait for admission (they are device
+        # memory outside the scheduler's budget)
+        if len(self._pending) >= self.fields_ahead:
+            return False
         if req.rid not in self._pending:
             self._pending[req.rid] = self._pool.submit(self.fields, req)
+        return True
 
     def _stream(self, method):
         if method not in self.streams:
@@ -256,11 +271,14 @@ class GpuBackend:
             # spectrum wait only for the batch steps it takes part in
             b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._torch.cuda.Stream())
             self.created += 1
-        with torch.cuda.stream(self._upload):
-            # a copy from pageable memory returns when it is done; the box's
-            # stream then waits for the upload stream, not the reverse
-            ud = torch.from_numpy(u).to("cuda")
-            b.init_velocity_field_device(ud)
+        if torch.is_tensor(u) and u.is_cuda:
+            b.init_velocity_field_device(u)   # made on the device, nothing to copy
+        else:
+            with torch.cuda.stream(self._upload):
+                # a copy from pageable memory returns when it is done; the
+                # box's stream then waits for the upload stream
+                ud = torch.from_numpy(np.ascontiguousarray(u)).to("cuda")
+                b.init_velocity_field_device(ud)
         self._runs += 1
         b.serve_run = self._runs
         return b

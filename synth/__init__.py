@@ -87,14 +87,16 @@ def dhit_field(n, seed, k0=4.0, u_rms=0.05):
     return np.ascontiguousarray(u * (u_rms / cur))
 
 
-def dhit_field_gpu(n, seed, k0=4.0, u_rms=0.05, device="cuda"):
+def dhit_field_gpu(n, seed, k0=4.0, u_rms=0.05, device="cuda", as_tensor=False):
     """`dhit_field` with its transforms and scalings done on a GPU through
     PyTorch: the same white noise (numpy PCG64 seeded with `seed`), the same
     steps in the same order; the shell energies are summed on the host
     (numpy bincount, a fixed order), so the result is the same bits on every
     call and agrees with `dhit_field` to the rounding of the two FFT
     implementations.  For callers that need many large fields quickly (a
-    256^3 field takes seconds on the host).  Returns a float64 numpy array."""
+    256^3 field takes seconds on the host).  Returns a float64 numpy array,
+    or with as_tensor the contiguous float64 device tensor (the work queued
+    on the calling thread's current stream done)."""
     import torch
     rng = np.random.default_rng(seed)
     noise = torch.from_numpy(rng.standard_normal((3, n, n, n))).to(device)
@@ -123,7 +125,11 @@ def dhit_field_gpu(n, seed, k0=4.0, u_rms=0.05, device="cuda"):
     uh = uh * torch.from_numpy(scale).to(device)[shell][None]
     u = torch.fft.ifftn(uh, dim=(1, 2, 3)).real
     cur = np.sqrt(float(torch.mean(torch.sum(u * u, dim=0))) / 3.0)
-    return np.ascontiguousarray((u * (u_rms / cur)).cpu().numpy())
+    u = (u * (u_rms / cur)).contiguous()
+    if as_tensor:
+        torch.cuda.current_stream().synchronize()
+        return u
+    return np.ascontiguousarray(u.cpu().numpy())
 
 
 def random_populations(n, seed, amplitude=1e-2):
