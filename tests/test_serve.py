@@ -338,3 +338,37 @@ def test_device_init_and_batch_stream_errors():
     with pytest.raises(dhit.DhitError) as e:
         _binding.batch_set_stream(None, 0)
     assert e.value.code == -1
+
+
+def test_prepare_may_decline_and_is_asked_again():
+    """A backend that holds at most two prepared requests declines the rest
+    (returns False); the scheduler asks again in later rounds, in arrival
+    order, and every request is still prepared before it starts."""
+    clock = FakeClock()
+
+    class Bounded(FakeBackend):
+        def __init__(self, clock):
+            super().__init__(clock, rate=1e6)
+            self.held, self.prepared, self.asked = set(), [], []
+
+        def prepare(self, req):
+            self.asked.append(req.rid)
+            if len(self.held) >= 2:
+                return False
+            self.held.add(req.rid)
+            self.prepared.append(req.rid)
+            return True
+
+        def start(self, req):
+            assert req.rid in self.held
+            self.held.discard(req.rid)
+            return super().start(req)
+
+    be = Bounded(clock)
+    trace = poisson_trace(20, 100.0, seed=8, grids=(16, 32), weights=(1, 1), steps=(50, 200))
+    sch = Scheduler(be, 1e12, max_active=2, chunk=25)
+    sch.run(trace, clock=clock, sleep=clock.sleep)
+    assert len(sch.results) == len(trace)
+    assert be.prepared == sorted(be.prepared)          # prepared in arrival order
+    assert sorted(be.prepared) == [r.rid for r in trace]
+    assert len(be.asked) > len(trace)                  # some were declined and asked again
