@@ -226,6 +226,8 @@ class GpuBackend:
         self._idle_total = 0
         self._runs = 0      # runs started (tells a reused box's runs apart in batch keys)
         self.created = 0    # boxes created (the rest of the runs reused a pooled box)
+        # host seconds inside start(): waiting for initial fields, creating boxes, initial states
+        self.start_s = dict(field_wait=0.0, create=0.0, init=0.0)
         if fields is None:
             import synth
             fields = lambda req: synth.dhit_field_gpu(req.n, seed=req.seed, k0=k0, u_rms=u_rms, as_tensor=True)
@@ -234,6 +236,17 @@ class GpuBackend:
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=field_workers)
         self._pending = {}   # rid -> future of the initial field (host array)
         self._upload = torch.cuda.Stream()
+
+    def warm_up(self, grids, methods=("mrt", "dugks")):
+        """What the first run of a grid size would otherwise pay at admission:
+        hipFFT plans of the library's spectrum (through spectrum_bytes) and of
+        the field recipe (one field made), whose kernels are compiled on first
+        use in the process."""
+        for n in grids:
+            for m in methods:
+                self.bytes_of(Request(0.0, -1, n, m, 0, 0))
+            self.fields(Request(0.0, -1, n, methods[0], 0, 0))
+        self._torch.cuda.synchronize()
 
     def prepare(self, req):
         # at most `fields_ahead` fields wait for admission (they are device
@@ -260,8 +273,10 @@ class GpuBackend:
 
     def start(self, req):
         torch = self._torch
+        t0 = time.perf_counter()
         fut = self._pending.pop(req.rid, None)
         u = fut.result() if fut is not None else self.fields(req)
+        t1 = time.perf_counter()
         idle = self._idle.get((req.n, req.method))
         if idle:
             b = idle.pop()
@@ -271,6 +286,7 @@ class GpuBackend:
             # spectrum wait only for the batch steps it takes part in
             b = self._Box(req.n, req.method, self.precision, self.nu, stream=self._torch.cuda.Stream())
             self.created += 1
+        t2 = time.perf_counter()
         if torch.is_tensor(u) and u.is_cuda:
             b.init_velocity_field_device(u)   # made on the device, nothing to copy
         else:
@@ -281,6 +297,10 @@ class GpuBackend:
                 b.init_velocity_field_device(ud)
         self._runs += 1
         b.serve_run = self._runs
+        t3 = time.perf_counter()
+        self.start_s["field_wait"] += t1 - t0
+        self.start_s["create"] += t2 - t1
+        self.start_s["init"] += t3 - t2
         return b
 
     def advance(self, boxes, nsteps):
