@@ -33,6 +33,9 @@
  *     asynchronous; calls that return host data synchronise that stream.
  *   - Thread safety: one box must not be used from two threads at once;
  *     different boxes are independent.
+ *   - Environment: every entry point first clears a HIP error that other
+ *     code left pending on the thread (DHIT_DEBUG=1 prints it to stderr);
+ *     DHIT_TUNE_CACHE names the batch autotuner's cache file (create_batch).
  */
 #ifndef DHIT_H
 #define DHIT_H
