@@ -311,6 +311,7 @@ def main():
     ap.add_argument("--nu", type=float, default=0.0025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sizes", action="store_true", help="skip the per-size GPU table (mlups_by_size)")
     ap.add_argument("--extras", nargs="?", const="all", default=None,
                     help="also run extra configurations (minutes): 'all' or a comma list of "
                          "ensemble, serving, precision, stability, mesh")
@@ -438,8 +439,9 @@ def main():
         line["mlups_fp32"] = {"combined": round(r["mlups"], 1), "lbe_mrt": round(r["mlups_lbe_mrt"], 1),
                               "dugks": round(r["mlups_dugks"], 1),
                               "speedup_vs_fp64": round(r["mlups"] / fp64["mlups"], 3)}
-    print("bench: per-size rates", file=sys.stderr, flush=True)
-    line["mlups_by_size"] = gpu_sizes(torch, dhit, nu)
+    if not args.no_sizes:
+        print("bench: per-size rates", file=sys.stderr, flush=True)
+        line["mlups_by_size"] = gpu_sizes(torch, dhit, nu)
     if args.extras:
         line["extras"] = extras(torch, dhit, args.extras)
     if not args.no_cpu_baseline:
