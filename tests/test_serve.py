@@ -260,13 +260,15 @@ def test_device_init_equals_host_init(method, precision):
 @pytest.mark.gpu
 def test_pooled_boxes_give_the_same_result():
     """At most two runs at a time, so later runs take the boxes of earlier
-    ones from the backend's pool (fewer boxes created than runs): every
-    result equals the same run alone on a fresh box, bit for bit."""
+    ones from the backend's pool: with one grid size and two methods at most
+    four boxes of a method are busy at once (two running, two waiting to be
+    finished), so 12 runs cannot need 12 boxes.  Every result equals the same
+    run alone on a fresh box, bit for bit."""
     import paper_1601_03815_amd as dhit
     import synth
     from paper_1601_03815_amd.serve import GpuBackend
 
-    trace = poisson_trace(8, 100.0, seed=21, grids=(8, 12), weights=(1, 1), steps=(20, 40))
+    trace = poisson_trace(12, 100.0, seed=21, grids=(12,), weights=(1,), steps=(20, 40))
     be = GpuBackend(precision="fp32", nu=0.01)
     sch = Scheduler(be, 4e9, max_active=2, chunk=8)
     stats = sch.run(trace)
