@@ -82,10 +82,20 @@ typedef struct dhit_params {
     int32_t variant;    /* enum dhit_variant */
     int32_t tile_width; /* fused DUGKS kernel: width of a block's column tile, 16 or 32
                            (0 = the default, 32) */
-    int32_t z_chunk;    /* fused DUGKS kernel: planes one block marches through,
-                           0 = chosen at create_box for the current device: the
-                           chunk ceil(n/k) >= min(n, 8) that minimises
-                           ceil(blocks / resident blocks) * (chunk + 2) */
+    int32_t z_chunk;    /* fused DUGKS kernel, planes one block marches through:
+                           c > 0: z-chunks of c planes (c <= n), one block per
+                           column tile and chunk;
+                           -c < 0: the same chunks, except that when they fill
+                           at least one round of the device's resident blocks
+                           and the last round at most half, each chunk of the
+                           last round is cut in z into min(slots / left-over
+                           chunks, c) parts, so that it fills the device;
+                           0 = chosen at create_box for the current device:
+                           among the chunks ceil(n/k) >= min(n, 8), plain or
+                           cut, the one that minimises the launch's estimated
+                           plane iterations per block.  Every setting gives
+                           the same populations; the global sums agree to
+                           rounding (the work split groups the cells' sums) */
     double nu;          /* kinematic viscosity, > 0 */
     double rho0;        /* mean density, > 0 (paper: 1) */
     double dt;          /* time step: LBE requires 1; DUGKS requires 0 < dt*sqrt(2) <= 1

@@ -76,7 +76,7 @@ void validate(const dhit_params &p) {
   if (p.precision != DHIT_FP64 && p.precision != DHIT_FP32) fail(DHIT_EINVAL, "unknown precision");
   if (p.variant != DHIT_VARIANT_DEFAULT && p.variant != DHIT_VARIANT_TWO_PASS) fail(DHIT_EINVAL, "unknown variant");
   if (p.tile_width != 0 && p.tile_width != 16 && p.tile_width != 32) fail(DHIT_EINVAL, "tile_width must be 0, 16 or 32");
-  if (p.z_chunk < 0 || p.z_chunk > p.n) fail(DHIT_EINVAL, "z_chunk must be in [0, n]");
+  if (p.z_chunk < -p.n || p.z_chunk > p.n) fail(DHIT_EINVAL, "z_chunk must be in [-n, n]");
   if (!(p.nu > 0) || !std::isfinite(p.nu)) fail(DHIT_EINVAL, "nu must be positive and finite");
   if (!(p.rho0 > 0) || !std::isfinite(p.rho0)) fail(DHIT_EINVAL, "rho0 must be positive and finite");
   if (p.method == DHIT_DUGKS) {

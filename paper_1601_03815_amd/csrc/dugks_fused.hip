@@ -58,7 +58,10 @@
 // ring (loads only).  Blocks are numbered so that the tiles one XCD (one L2)
 // works on at a time are neighbours, whose halo columns then come from that
 // L2.
+#include <array>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "collision.hpp"
 
@@ -472,19 +475,18 @@ __device__ __forceinline__ void publish_cell(const Real (&f)[kQ], Real *P, Real 
   });
 }
 
-// The z-march of one tile (bx, by) over the z-chunk bz of a box; adds the
-// moments of the updated cells to v.  L is the block's LDS, kFusedValues
+// The z-march of one tile (bx, by) over the planes [z0, z1) of a box; adds
+// the moments of the updated cells to v.  L is the block's LDS, kFusedValues
 // values per column: P [kNPop][NT], Q [2][kNQ][NT], Z [3][kNZ][NT].
 template <typename Real, int W, bool O32>
 __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
-                                           int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
+                                           int bx, int by, int z0, int z1, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   const int n = p.n;
   const int64_t stride = p.stride;
   const int tid = tile_column<W>(threadIdx.x);  // column of the tile
   const int tx = tid % TX, ty = tid / TX;
-  const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
-  const int z1 = min(z0 + nz_chunk, n);
+  const int x0 = bx * IX, y0 = by * IY;
   int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
   gx = gx < 0 ? gx + n : (gx >= n ? gx % n : gx);
   gy = gy < 0 ? gy + n : (gy >= n ? gy % n : gy);
@@ -708,6 +710,49 @@ __device__ __forceinline__ void fused_tile(const global_t<Real> *__restrict__ ft
 template <typename Real>
 constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
 
+// Tile and planes of work item `local` of a box.  Items are tile z-chunks,
+// numbered by tile (x fastest, then y), then by chunk.  With tail_split =
+// m > 1 (a box launched alone, one block per item, blocks dealt to the 8
+// XCDs in turn): the first tail_from chunk items fill whole rounds of the
+// device; each of the t chunks left over is cut in z into m parts of
+// ceil(chunk planes / m) planes (the last parts may be short or empty),
+// numbered part by part so that the parts of neighbouring tiles run side by
+// side.  The work of each XCD (a contiguous eighth of the items, see
+// xcd_tile) is its eighth of the whole chunks followed by its eighth of the
+// parts (slots past the last part are empty), so that every XCD's last
+// round is made of parts and fills its compute units for a fraction of a
+// chunk's time.
+struct ItemPlanes {
+  int tile, z0, left;
+  __device__ __forceinline__ ItemPlanes(const BatchBox &d, int local) {
+    const int n = d.sp.n, c = d.nz_chunk, tiles = d.tiles_x * d.tiles_y;
+    int item = local, part = 0, parts = 1;
+    if (d.tail_split > 1) {
+      const int t = tiles * ((n + c - 1) / c) - d.tail_from;
+      const int pieces = t * d.tail_split;
+      const int fx = d.tail_from / 8, px = (pieces + 7) / 8;
+      const int x = local / (fx + px), j = local - x * (fx + px);
+      if (j < fx) {
+        item = x * fx + j;
+      } else {
+        const int piece = x * px + (j - fx);
+        if (piece >= pieces) {  // an empty slot of the last XCD
+          tile = z0 = left = 0;
+          return;
+        }
+        part = piece / t;
+        item = d.tail_from + (piece - part * t);
+        parts = d.tail_split;
+      }
+    }
+    tile = item % tiles;
+    const int zc = item / tiles * c, zc1 = min(zc + c, n);
+    const int len = (zc1 - zc + parts - 1) / parts;
+    z0 = min(zc1, zc + part * len);
+    left = min(zc1, z0 + len) - z0;
+  }
+};
+
 // Tile of a block, numbered so that the blocks one XCD runs (blocks are
 // dealt to the eight XCDs in turn) take consecutive tiles: block b of a
 // launch of `padded` blocks (a multiple of 8) takes tile
@@ -731,13 +776,13 @@ __global__ __launch_bounds__(Tile<W>::NT, kWavesPerSimd<Real>) void dugks_fused_
     const int b = find_batch_box(boxes, nbox, it);
     const BatchBox &d = boxes[b];
     const int local = it - d.item_begin;
-    const int bx = local % d.tiles_x;
-    const int by = (local / d.tiles_x) % d.tiles_y;
-    const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
-    fused_tile<Real, W, O32>(to_global(static_cast<const Real *>(d.f[d.cur])), to_global(static_cast<Real *>(d.f[d.cur ^ 1])), d.sp, bx, by, bz,
-                        d.nz_chunk, L, v);
+    const global_t<Real> *src = to_global(static_cast<const Real *>(d.f[d.cur]));
+    global_t<Real> *dst = to_global(static_cast<Real *>(d.f[d.cur ^ 1]));
+    const ItemPlanes ip(d, local);
     // the march ends with a barrier: L is free for the block reduction
+    if (ip.left > 0)
+      fused_tile<Real, W, O32>(src, dst, d.sp, ip.tile % d.tiles_x, ip.tile / d.tiles_x, ip.z0, ip.z0 + ip.left, L, v);
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
   }
@@ -844,19 +889,18 @@ __device__ __forceinline__ void publish_group(const Real (&f)[Group<G>::N], cons
   });
 }
 
-// The z-march of group G of a tile (see above).  L: the block's LDS,
-// kSplitValues values per column.
+// The z-march of group G of a tile over the planes [z0, z1) (see above).
+// L: the block's LDS, kSplitValues values per column.
 template <typename Real, int W, int G, bool O32>
 __device__ __forceinline__ void split_tile(const global_t<Real> *__restrict__ ft, global_t<Real> *__restrict__ out, const StepParams &p,
-                                           int bx, int by, int bz, int nz_chunk, Real *L, double (&v)[kNumSums]) {
+                                           int bx, int by, int z0, int z1, Real *L, double (&v)[kNumSums]) {
   constexpr int TX = Tile<W>::TX, TY = Tile<W>::TY, IX = Tile<W>::IX, IY = Tile<W>::IY, NT = Tile<W>::NT;
   constexpr int NG = Group<G>::N;
   const int n = p.n;
   const int64_t stride = p.stride;
   const int c = tile_column<W>(threadIdx.x - G * NT);  // column of the tile
   const int tx = c % TX, ty = c / TX;
-  const int x0 = bx * IX, y0 = by * IY, z0 = bz * nz_chunk;
-  const int z1 = min(z0 + nz_chunk, n);
+  const int x0 = bx * IX, y0 = by * IY;
   int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
   gx = gx < 0 ? gx + n : (gx >= n ? gx % n : gx);
   gy = gy < 0 ? gy + n : (gy >= n ? gy % n : gy);
@@ -1131,16 +1175,17 @@ __global__ __launch_bounds__(2 * Tile<W>::NT) void dugks_split_kernel(const Batc
     const int b = find_batch_box(boxes, nbox, it);
     const BatchBox &d = boxes[b];
     const int local = it - d.item_begin;
-    const int bx = local % d.tiles_x;
-    const int by = (local / d.tiles_x) % d.tiles_y;
-    const int bz = local / (d.tiles_x * d.tiles_y);
     double v[kNumSums] = {0, 0, 0, 0, 0};
     const global_t<Real> *src = to_global(static_cast<const Real *>(d.f[d.cur]));
     global_t<Real> *dst = to_global(static_cast<Real *>(d.f[d.cur ^ 1]));
-    if (threadIdx.x < Tile<W>::NT)
-      split_tile<Real, W, 0, O32>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
-    else
-      split_tile<Real, W, 1, O32>(src, dst, d.sp, bx, by, bz, d.nz_chunk, L, v);
+    const ItemPlanes ip(d, local);
+    if (ip.left > 0) {
+      const int bx = ip.tile % d.tiles_x, by = ip.tile / d.tiles_x, z1 = ip.z0 + ip.left;
+      if (threadIdx.x < Tile<W>::NT)
+        split_tile<Real, W, 0, O32>(src, dst, d.sp, bx, by, ip.z0, z1, L, v);
+      else
+        split_tile<Real, W, 1, O32>(src, dst, d.sp, bx, by, ip.z0, z1, L, v);
+    }
     write_block_partials(v, d.partials, d.items, local, reinterpret_cast<double (*)[kNumSums]>(L));
     __syncthreads();
   }
@@ -1165,6 +1210,8 @@ constexpr int fused_tile_width(int) { return 32; }
 
 int fused_default_chunk(int n) { return n >= 128 ? 32 : (n >= 32 ? 16 : n); }
 
+// Chunk items of a box (tiles x z-chunks) at tile width w and z-chunk
+// `chunk` planes, and its tiling.
 int fused_dugks_items(int n, int w, int chunk, int *tiles_x, int *tiles_y) {
   const int ix = w - 2, iy = 8 - 2;
   const int tx = (n + ix - 1) / ix;
@@ -1178,17 +1225,54 @@ int fused_dugks_items(int n, int w, int chunk, int *tiles_x, int *tiles_y) {
 // the two halo planes too often).
 constexpr int kMinAutoChunk = 8;
 
-// Tiles of a single-box fused launch with the box's tile width and z-chunk
-// (one block per tile; the grid is rounded up to a multiple of 8).  With
-// z_chunk = 0 (not yet resolved) the count is that of the shortest chunk
-// the balanced choice can take, an upper bound for sizing buffers.
-int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
+// Parts each chunk of a launch's last round is cut into: `chunks` items of
+// `chunk` planes run in rounds of `slots` blocks; when at least one round
+// is full and the t items left over fill at most half a round, each is cut
+// into min(slots / t, chunk) parts (1: no cut).
+static int tail_parts(int chunks, int slots, int chunk) {
+  const int full = chunks / slots, t = chunks - full * slots;
+  if (full < 1 || t == 0) return 1;
+  const int m = std::min(slots / t, chunk);
+  return m >= 2 ? m : 1;
+}
+
+static int fused_slots(int precision, int w);
+
+FusedPlan fused_plan(const dhit_params &p) {
+  FusedPlan f{};
   const int n = p.n;
-  const int w = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
-  const int cz = p.z_chunk ? p.z_chunk : std::min(n, kMinAutoChunk);
-  if (width) *width = w;
-  if (nz_chunk) *nz_chunk = cz;
-  return fused_dugks_items(n, w, cz, tiles_x, tiles_y);
+  f.width = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
+  // an unresolved setting (0) gets the shortest automatic chunk: an upper
+  // bound on the items, for sizing buffers
+  f.chunk = p.z_chunk > 0 ? p.z_chunk : (p.z_chunk < 0 ? -p.z_chunk : std::min(n, kMinAutoChunk));
+  const int chunks = fused_dugks_items(n, f.width, f.chunk, &f.tiles_x, &f.tiles_y);
+  f.items = f.tail_from = f.grid = chunks;
+  f.tail_split = 1;
+  if (p.z_chunk < 0) {
+    const int slots = fused_slots(p.precision, f.width);
+    const int m = tail_parts(chunks, slots, f.chunk);
+    if (m > 1 && slots % 8 == 0) {
+      f.tail_from = chunks / slots * slots;
+      f.tail_split = m;
+      // per XCD: its eighth of the whole chunks, then its eighth of the parts
+      const int pieces = (chunks - f.tail_from) * m;
+      f.items = f.grid = 8 * (f.tail_from / 8 + (pieces + 7) / 8);
+    }
+  }
+  return f;
+}
+
+// Work items of a box's fused launch (and its tiling).  With z_chunk = 0
+// (not yet resolved) an upper bound for sizing buffers: twice the items of
+// the shortest automatic chunk and 8 (a cut last round adds at most a
+// round's items, rounded up to a multiple of 8, to at least one full round).
+int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk) {
+  const FusedPlan f = fused_plan(p);
+  if (width) *width = f.width;
+  if (tiles_x) *tiles_x = f.tiles_x;
+  if (tiles_y) *tiles_y = f.tiles_y;
+  if (nz_chunk) *nz_chunk = f.chunk;
+  return p.z_chunk == 0 ? 2 * f.items + 8 : f.items;
 }
 
 // FP64 tiles use the split-population march (two thread groups per
@@ -1234,8 +1318,7 @@ void launch_dugks_batch(hipStream_t s, int precision, int w, int max_n, const Ba
 
 // The two one-box tables of a box: entry c steps from f[c] to f[1 - c].
 void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]) {
-  int w, tx, ty, cz;
-  const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
+  const FusedPlan f = fused_plan(b.p);
   for (int c = 0; c < 2; ++c) {
     std::memset(&e[c], 0, sizeof(BatchBox));
     e[c].f[0] = b.f[0];
@@ -1243,10 +1326,12 @@ void fused_table_entries(const dhit_box &b, BatchBox (&e)[2]) {
     e[c].sp = b.sp;
     e[c].ncell = (int)b.ncell;
     e[c].item_begin = 0;
-    e[c].items = tiles;
-    e[c].tiles_x = tx;
-    e[c].tiles_y = ty;
-    e[c].nz_chunk = cz;
+    e[c].items = f.items;
+    e[c].tiles_x = f.tiles_x;
+    e[c].tiles_y = f.tiles_y;
+    e[c].nz_chunk = f.chunk;
+    e[c].tail_from = f.tail_from;
+    e[c].tail_split = f.tail_split;
     e[c].partials = b.partials;
     e[c].hist = b.hist;
     e[c].cur = c;
@@ -1264,14 +1349,13 @@ static void fused_step(dhit_box &b, const void *src, void *dst, double *sums_out
   if (src == b.f[0] && dst == b.f[1]) entry = 0;
   else if (src == b.f[1] && dst == b.f[0]) entry = 1;
   else throw Error(DHIT_EINVAL, "fused DUGKS step between buffers that are not the box's");
-  int w, tx, ty, cz;
-  const int tiles = fused_dugks_blocks(b.p, &w, &tx, &ty, &cz);
+  const FusedPlan f = fused_plan(b.p);
   {
     TimedLaunch t(b, DHIT_K_DUGKS_FUSED);
-    launch_dugks_batch(b.stream, b.p.precision, w, b.n, b.step_table + entry, 1, tiles, tiles);
+    launch_dugks_batch(b.stream, b.p.precision, f.width, b.n, b.step_table + entry, 1, f.items, f.grid);
     t.done();
   }
-  launch_finalize_sums(b, b.partials, tiles, sums_out);
+  launch_finalize_sums(b, b.partials, f.items, sums_out);
 }
 
 int fused_tile_width_of(int precision) { return fused_tile_width(precision); }
@@ -1297,13 +1381,36 @@ static int fused_resident_blocks(int precision, int w) {
 
 int fused_resident_blocks_of(int precision, int w) { return fused_resident_blocks(precision, w); }
 
+// Blocks of the fused kernel that the current device holds at once
+// (compute units x resident blocks), kept per device.
+static int fused_slots(int precision, int w) {
+  int dev = 0;
+  DHIT_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::array<int, 3>, int> known;
+  std::lock_guard<std::mutex> lock(mu);
+  const std::array<int, 3> key{dev, precision, w};
+  const auto it = known.find(key);
+  if (it != known.end()) return it->second;
+  int cus = 0;
+  DHIT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int slots = std::max(cus, 1) * fused_resident_blocks(precision, w);
+  known[key] = slots;
+  return slots;
+}
+
 // z-chunk that balances a launch.  Its blocks run in rounds of `slots`
 // (compute units x resident blocks); a block marching c planes costs about
-// c + 2 plane iterations (the two halo planes), so the launch costs about
-// ceil(blocks / slots) (c + 2).  Among the chunks ceil(n / k) of at least
-// kMinAutoChunk planes (or n, if smaller) the cheapest is taken, the
-// longest of equal ones.  At 256^3 this picks 37 planes in FP64 (1 block
-// per unit, 387 column tiles: 11 rounds of 39 against 13 of 34 for 32).
+// c + 2 plane iterations (the two halo planes), so a launch of K chunk items
+// costs about ceil(K / slots) (c + 2); with its last, partly filled round
+// cut into m parts per chunk (tail_parts) it costs floor(K / slots) (c + 2)
+// + ceil(c / m) + 2.  Among the chunks ceil(n / k) of at least kMinAutoChunk
+// planes (or n, if smaller), each with and without the cut, the cheapest is
+// taken (the cut one is returned as -c), the longest and the uncut of equal
+// ones.  At 256^3 in FP64 (1 block per unit, 387 column tiles): chunks of
+// 37 planes cost 11 rounds of 39 iterations (the last round 58% full: 429);
+// chunks of 128 planes, 3 full rounds of 130 and 6 chunks left over that
+// are cut into 42 parts of 4 planes, 396.
 int fused_balanced_chunk(int n, int tiles_xy, int slots) {
   const int cmin = std::min(n, kMinAutoChunk);
   int best = n;
@@ -1317,18 +1424,24 @@ int fused_balanced_chunk(int n, int tiles_xy, int slots) {
       best_cost = cost;
       best = c;
     }
+    if (blocks <= INT32_MAX) {
+      const int m = tail_parts((int)blocks, slots, c);
+      const int64_t cut = blocks / slots * (c + 2) + (c + m - 1) / m + 2;
+      if (m > 1 && cut < best_cost) {
+        best_cost = cut;
+        best = -c;
+      }
+    }
   }
   return best;
 }
 
 // Default z-chunk of a box on the current device.
 int fused_auto_chunk(const dhit_params &p) {
-  int w, tx, ty;
-  fused_dugks_blocks(p, &w, &tx, &ty, nullptr);
-  int dev = 0, cus = 0;
-  DHIT_HIP(hipGetDevice(&dev));
-  DHIT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  return fused_balanced_chunk(p.n, tx * ty, std::max(cus, 1) * fused_resident_blocks(p.precision, w));
+  dhit_params q = p;
+  q.z_chunk = 0;
+  const FusedPlan f = fused_plan(q);
+  return fused_balanced_chunk(p.n, f.tiles_x * f.tiles_y, fused_slots(p.precision, f.width));
 }
 
 void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out) { fused_step(b, src, dst, sums_out); }

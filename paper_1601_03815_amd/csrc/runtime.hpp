@@ -67,6 +67,9 @@ struct BatchBox {
   int item_begin;      // first work item of the box in the batch
   int items;           // work items of the box (= blocks of its single-box launch)
   int tiles_x, tiles_y, nz_chunk;  // DUGKS tiling
+  // DUGKS: with tail_split > 1 the chunk items from tail_from on are each
+  // cut into tail_split parts in z (see ItemPlanes in dugks_fused.hip)
+  int tail_from, tail_split;
   double *partials;    // the box's per-item partial sums, [5][items]
   double *hist;        // the box's history of global sums, [kHistoryCap][5]
   double *trial;       // where a trial (uncommitted) step writes its sums, [5]
@@ -136,6 +139,14 @@ void launch_dugks_step(dhit_box &b, const void *src, void *dst, double *sums_out
 void launch_dugks_fused(dhit_box &b, const void *src, void *dst, double *sums_out);
 // Blocks of the fused DUGKS launch for an n^3 box (and its tiling).
 int fused_dugks_blocks(const dhit_params &p, int *width, int *tiles_x, int *tiles_y, int *nz_chunk);
+// Work split of a box's fused DUGKS launch: tile width, tiling, z-chunk,
+// work items (the chunk items, or with a cut last round tail_from whole
+// chunks and the (chunk items - tail_from) * tail_split parts, laid out
+// per XCD) and grid (one block per item).
+struct FusedPlan {
+  int width, tiles_x, tiles_y, chunk, items, tail_from, tail_split, grid;
+};
+FusedPlan fused_plan(const dhit_params &p);
 void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst);
 void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
 // One pass of the LBE initial-state iteration on state f (in place): momentum

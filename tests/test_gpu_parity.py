@@ -460,7 +460,7 @@ def test_batch_rejects_mixed_boxes():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("tile,chunk", [(16, 0), (32, 0), (16, 5), (32, 7), (16, 1)])
+@pytest.mark.parametrize("tile,chunk", [(16, 0), (32, 0), (16, 5), (32, 7), (16, 1), (32, -5)])
 def test_dugks_tile_and_chunk_settings(precision, tile, chunk):
     """Every tile width and z-chunk (including chunks that do not divide n
     and single-plane chunks) gives the same step."""
@@ -474,6 +474,35 @@ def test_dugks_tile_and_chunk_settings(precision, tile, chunk):
         got = box.get_populations()
     ref = O.dugks_step(f0, nu=nu, nsteps=2)
     assert rel_err(got, ref) <= (TOL64 if precision == "fp64" else 2 * TOL32)
+
+
+@pytest.mark.parametrize("precision,chunks", [("fp64", (7, -7, -2)), ("fp32", (3, -3, -2))])
+def test_dugks_cut_last_round(precision, chunks):
+    """A negative z_chunk launches the chunks on as many blocks as the device
+    holds and cuts each chunk of a last, at most half full round into parts.
+    At 64^3 with 32-wide tiles (33 column tiles) on a device of 256 compute
+    units: FP64 (one block per unit) 7-plane chunks leave 74 chunks after one
+    full round, cut into parts of 3, 3 and 1 planes (the last chunk, one
+    plane, into 1, 0 and 0); 2-plane chunks leave 32 after four rounds; FP32
+    (two blocks per unit) 3-plane chunks leave 214 after one round, cut in
+    two.  Each split gives the oracle's two steps, the same populations as
+    the uncut chunk bit for bit, and global sums equal to rounding."""
+    n, nu = 64, 0.01
+    f0 = synth.random_populations(n, seed=78, amplitude=0.01)
+    if precision == "fp32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    ref = O.dugks_step(f0, nu=nu, nsteps=2)
+    pops, hists = [], []
+    for chunk in chunks:
+        with dhit.Box(n, "dugks", precision, nu, tile_width=32, z_chunk=chunk) as box:
+            box.set_populations(f0)
+            box.step(2)
+            pops.append(box.get_populations())
+            hists.append(box.sums_history(2))
+    assert rel_err(pops[0], ref) <= (TOL64 if precision == "fp64" else 2 * TOL32)
+    for p, h in zip(pops[1:], hists[1:]):
+        np.testing.assert_array_equal(p, pops[0])
+        np.testing.assert_allclose(h, hists[0], rtol=0, atol=1e-12 * np.abs(f0).sum())
 
 
 @pytest.mark.gpu
