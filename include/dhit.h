@@ -293,9 +293,10 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
 
 /* Batches: many boxes of one method and precision advanced together
  * (an ensemble of independent runs, e.g. of different grid sizes).
- * Each step is one persistent kernel launch over a work list spanning all
- * boxes (LBE: runs of 256 cells, or 512 when every box's n is even in FP64,
- * two cells per thread; DUGKS: tile z-chunks of the fused kernel)
+ * Each step is one kernel launch over a work list spanning all boxes (LBE:
+ * runs of 256 cells, or 512 when every box's n is even in FP64, two cells
+ * per thread; DUGKS: tile z-chunks of the fused kernel), on a grid of one
+ * block per work item or on a persistent grid whose blocks loop over them,
  * followed by one launch that finalises every box's global sums; the
  * per-box buffer index and step counter are kept on the device, so runs of
  * 8 steps are replayed from one captured hipGraph.  Results equal
@@ -306,15 +307,16 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * sums are grouped).
  *
  * create_batch: boxes[nbox] must share method and precision (DUGKS boxes the
- * default variant) and appear once.  With autotune != 0 the persistent grid
- * size and, for DUGKS, the column-tile width (16 or 32) and work-item
+ * default variant) and appear once.  With autotune != 0 the grid (one block
+ * per work item, or a persistent grid of 1 to 32 blocks per compute unit)
+ * and, for DUGKS, the column-tile width (16 or 32) and work-item
  * z-chunk are chosen by timing uncommitted trial steps on the boxes
  * themselves (their states are left unchanged); choices are cached per
  * process under (method, precision, compute units of the device, grid
  * sizes) and, if the environment variable DHIT_TUNE_CACHE names a file,
  * read from and appended to it (one line per choice: key, grid, chunk,
  * tile).  Without autotuning a DUGKS batch uses tile width 32 and as many
- * blocks as the device holds at once (LBE: eight per compute unit).  Work is
+ * blocks as the device holds at once (LBE: one block per work item).  Work is
  * issued on the first box's stream (or the one batch_set_stream names); on
  * the device, each batch step waits for the work queued on the boxes' own
  * streams before it, and the boxes' streams wait for the step after it (the
@@ -346,7 +348,7 @@ int32_t batch_set_stream(dhit_batch *bt, void *stream);
  * pinned copies, so the call waits at most for the upload two calls back. */
 int32_t batch_step(dhit_batch *bt, int32_t nsteps);
 
-/* info[6] = (persistent grid size, DUGKS z-chunk (0 = per-box default),
+/* info[6] = (grid size, DUGKS z-chunk (0 = per-box default),
  * work items per step, steps per graph replay, 1 if autotuned, DUGKS
  * column-tile width (0 for LBE)). */
 int32_t batch_info(const dhit_batch *bt, int64_t *info);
