@@ -310,7 +310,9 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride);
  * default variant) and appear once.  With autotune != 0 the grid (one block
  * per work item, or a persistent grid of 1 to 32 blocks per compute unit)
  * and, for DUGKS, the column-tile width (16 or 32) and work-item
- * z-chunk are chosen by timing uncommitted trial steps on the boxes
+ * z-chunk (8, 16 or 32 planes, or per box n planes below n = 32, 16 below
+ * n = 128 and 32 from there on, the untuned batch's chunks) are chosen by
+ * timing uncommitted trial steps on the boxes
  * themselves (their states are left unchanged); choices are cached per
  * process under (method, precision, compute units of the device, grid
  * sizes) and, if the environment variable DHIT_TUNE_CACHE names a file,
