@@ -88,8 +88,9 @@ typedef struct dhit_params {
                            -c < 0: the same chunks, except that when they fill
                            at least one round of the device's resident blocks
                            and the last round at most half, each chunk of the
-                           last round is cut in z into min(slots / left-over
-                           chunks, c) parts, so that it fills the device;
+                           last round is cut in z into parts of
+                           ceil(c / min(slots / left-over chunks, c)) planes,
+                           so that the round fills the device;
                            0 = chosen at create_box for the current device:
                            among the chunks ceil(n/k) >= min(n, 8), plain or
                            cut, the one that minimises the launch's estimated
@@ -135,6 +136,24 @@ int64_t box_bytes(const dhit_params *p);
  * without allocation).  For schedulers that admit boxes by HBM budget and
  * take diagnostics before releasing them.  A negative status on error. */
 int64_t spectrum_bytes(const dhit_params *p);
+
+/* Work split of the fused DUGKS step (Sec. II.A update, marched in z by
+ * column tiles; the z_chunk field above) of a box with parameters *p, on a
+ * device that holds `slots` blocks of the fused kernel at once (compute
+ * units x resident blocks: 256 or 512 on a 256-unit device, by precision).
+ * Host computation only, for tools and tests; needs no device.
+ * fused_work_items: returns the number of work items (one block each) of
+ * the step's launch, or a negative status; *z_chunk (may be NULL) receives
+ * the setting in effect (p->z_chunk, or the automatic choice for `slots`).
+ * fused_work_item: the column tile (numbered x fastest, then y; tiles of
+ * tile_width - 2 by 6 updated columns) and the planes [*z0, *z0 + *planes)
+ * that item `item` marches (*planes = 0: an empty slot).  Every tile-plane
+ * of the box belongs to exactly one item.  Errors: DHIT_EINVAL for null
+ * pointers, invalid parameters (as create_box), slots < 1 or an item out of
+ * range; DHIT_EMETHOD for an LBE box or the two-pass variant. */
+int32_t fused_work_items(const dhit_params *p, int32_t slots, int32_t *z_chunk);
+int32_t fused_work_item(const dhit_params *p, int32_t slots, int32_t item, int32_t *tile, int32_t *z0,
+                        int32_t *planes);
 
 /* Create a box.  Validates *p; on success *out owns the new box. */
 int32_t create_box(const dhit_params *p, dhit_box **out);

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     init_consistent, set_mesh, last_error,
     moments, vorticity, initial_pressure, population_buffer_bytes, set_populations, step_batch, step_dugks, step_lbe, steps_taken,
     sums_history, set_kernel_timing, read_kernel_timings, device_copy, step_noalloc, KERNEL_NAMES,
+    fused_work_items, fused_work_item,
     create_batch, batch_update, batch_set_stream, batch_step, batch_info, destroy_batch,
 )
 from . import _binding

@@ -77,6 +77,8 @@ def _load():
         "population_buffer_bytes": ([P], i64),
         "box_bytes": ([P], i64),
         "spectrum_bytes": ([P], i64),
+        "fused_work_items": ([P, i32, ctypes.POINTER(i32)], i32),
+        "fused_work_item": ([P, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "create_box": ([P, ctypes.POINTER(ctypes.c_void_p)], i32),
         "destroy_box": ([box], i32),
         "init_velocity_field": ([box, dp, dp], i32),
@@ -170,6 +172,22 @@ def box_bytes(p):
 
 def spectrum_bytes(p):
     return _check(_lib.spectrum_bytes(ctypes.byref(p)))
+
+
+def fused_work_items(p, slots):
+    """(work items of the fused DUGKS launch, z_chunk setting in effect) on a
+    device holding `slots` blocks of the kernel at once."""
+    z = ctypes.c_int32()
+    items = _check(_lib.fused_work_items(ctypes.byref(p), int(slots), ctypes.byref(z)))
+    return items, z.value
+
+
+def fused_work_item(p, slots, item):
+    """(tile, z0, planes) that work item `item` of that launch marches."""
+    t, z, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.fused_work_item(ctypes.byref(p), int(slots), int(item), ctypes.byref(t), ctypes.byref(z),
+                                ctypes.byref(k)))
+    return t.value, z.value, k.value
 
 
 def create_box(p):
@@ -351,7 +369,8 @@ def step_noalloc(p, src_ptr, dst_ptr, sums_ptr=None):
 
 
 EXPORTED = [
-    "default_params", "population_buffer_bytes", "box_bytes", "spectrum_bytes", "create_box", "destroy_box",
+    "default_params", "population_buffer_bytes", "box_bytes", "spectrum_bytes", "fused_work_items",
+    "fused_work_item", "create_box", "destroy_box",
     "init_velocity_field", "init_velocity_field_device", "init_consistent", "set_mesh", "step_lbe", "step_dugks", "moments", "sums_history", "energy_spectrum", "vorticity", "initial_pressure",
     "get_populations", "set_populations", "steps_taken", "box_synchronize", "current_populations",
     "step_batch", "create_batch", "batch_update", "batch_set_stream", "batch_step", "batch_info", "destroy_batch",

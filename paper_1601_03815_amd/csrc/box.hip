@@ -728,6 +728,54 @@ int32_t current_populations(const dhit_box *b, void **ptr, int64_t *stride) {
   });
 }
 
+namespace {
+// The fused DUGKS launch of params p on a device holding `slots` blocks of
+// the kernel at once, with an automatic z-chunk resolved for that device
+// (the resolved setting in *z_chunk).
+dhit::FusedPlan work_split_plan(const dhit_params *pp, int32_t slots, int32_t *z_chunk) {
+  if (!pp) fail(DHIT_EINVAL, "null params");
+  validate(*pp);
+  if (pp->method != DHIT_DUGKS || pp->variant != DHIT_VARIANT_DEFAULT)
+    fail(DHIT_EMETHOD, "the work split is that of the fused DUGKS step");
+  if (slots < 1) fail(DHIT_EINVAL, "slots must be positive");
+  dhit_params p = *pp;
+  if (p.z_chunk == 0) {
+    const dhit::FusedPlan t = dhit::fused_plan_for(p, slots);
+    p.z_chunk = dhit::fused_balanced_chunk(p.n, t.tiles_x * t.tiles_y, slots);
+  }
+  *z_chunk = p.z_chunk;
+  return dhit::fused_plan_for(p, slots);
+}
+}  // namespace
+
+int32_t fused_work_items(const dhit_params *p, int32_t slots, int32_t *z_chunk) {
+  int32_t items = 0;
+  const int32_t st = guarded([&]() -> int32_t {
+    int32_t zc = 0;
+    const dhit::FusedPlan f = work_split_plan(p, slots, &zc);
+    items = f.items;
+    if (z_chunk) *z_chunk = zc;
+    return DHIT_OK;
+  });
+  return st == DHIT_OK ? items : st;
+}
+
+int32_t fused_work_item(const dhit_params *p, int32_t slots, int32_t item, int32_t *tile, int32_t *z0,
+                        int32_t *planes) {
+  return guarded([&]() -> int32_t {
+    if (!tile || !z0 || !planes) fail(DHIT_EINVAL, "null argument");
+    int32_t zc = 0;
+    const dhit::FusedPlan f = work_split_plan(p, slots, &zc);
+    if (item < 0 || item >= f.items) fail(DHIT_EINVAL, "item out of range");
+    int t, z, k;
+    dhit::fused_item_planes(f, p->n, item, &t, &z, &k);
+    *tile = t;
+    *z0 = z;
+    *planes = k;
+    return DHIT_OK;
+  });
+}
+
 const char *dhit_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

@@ -722,9 +722,11 @@ constexpr int kWavesPerSimd = sizeof(Real) == 4 ? 2 : 1;
 // parts (slots past the last part are empty), so that every XCD's last
 // round is made of parts and fills its compute units for a fraction of a
 // chunk's time.
+// (Host and device code: the library's work-split query runs it on the host.)
+__host__ __device__ constexpr int imin(int a, int b) { return a < b ? a : b; }
 struct ItemPlanes {
   int tile, z0, left;
-  __device__ __forceinline__ ItemPlanes(const BatchBox &d, int local) {
+  __host__ __device__ __forceinline__ ItemPlanes(const BatchBox &d, int local) {
     const int n = d.sp.n, c = d.nz_chunk, tiles = d.tiles_x * d.tiles_y;
     int item = local, part = 0, parts = 1;
     if (d.tail_split > 1) {
@@ -746,10 +748,10 @@ struct ItemPlanes {
       }
     }
     tile = item % tiles;
-    const int zc = item / tiles * c, zc1 = min(zc + c, n);
+    const int zc = item / tiles * c, zc1 = imin(zc + c, n);
     const int len = (zc1 - zc + parts - 1) / parts;
-    z0 = min(zc1, zc + part * len);
-    left = min(zc1, z0 + len) - z0;
+    z0 = imin(zc1, zc + part * len);
+    left = imin(zc1, z0 + len) - z0;
   }
 };
 
@@ -1228,17 +1230,20 @@ constexpr int kMinAutoChunk = 8;
 // Parts each chunk of a launch's last round is cut into: `chunks` items of
 // `chunk` planes run in rounds of `slots` blocks; when at least one round
 // is full and the t items left over fill at most half a round, each is cut
-// into min(slots / t, chunk) parts (1: no cut).
+// into parts of ceil(chunk / min(slots / t, chunk)) planes, as many as that
+// length needs (1: no cut).
 static int tail_parts(int chunks, int slots, int chunk) {
   const int full = chunks / slots, t = chunks - full * slots;
   if (full < 1 || t == 0) return 1;
   const int m = std::min(slots / t, chunk);
-  return m >= 2 ? m : 1;
+  if (m < 2) return 1;
+  const int len = (chunk + m - 1) / m;
+  return (chunk + len - 1) / len;
 }
 
 static int fused_slots(int precision, int w);
 
-FusedPlan fused_plan(const dhit_params &p) {
+FusedPlan fused_plan_for(const dhit_params &p, int slots) {
   FusedPlan f{};
   const int n = p.n;
   f.width = p.tile_width ? p.tile_width : fused_tile_width(p.precision);
@@ -1248,8 +1253,7 @@ FusedPlan fused_plan(const dhit_params &p) {
   const int chunks = fused_dugks_items(n, f.width, f.chunk, &f.tiles_x, &f.tiles_y);
   f.items = f.tail_from = f.grid = chunks;
   f.tail_split = 1;
-  if (p.z_chunk < 0) {
-    const int slots = fused_slots(p.precision, f.width);
+  if (p.z_chunk < 0 && slots > 0) {
     const int m = tail_parts(chunks, slots, f.chunk);
     if (m > 1 && slots % 8 == 0) {
       f.tail_from = chunks / slots * slots;
@@ -1260,6 +1264,25 @@ FusedPlan fused_plan(const dhit_params &p) {
     }
   }
   return f;
+}
+
+FusedPlan fused_plan(const dhit_params &p) {
+  return fused_plan_for(p, p.z_chunk < 0 ? fused_slots(p.precision, p.tile_width ? p.tile_width : fused_tile_width(p.precision)) : 0);
+}
+
+void fused_item_planes(const FusedPlan &f, int n, int item, int *tile, int *z0, int *planes) {
+  BatchBox d;
+  std::memset(&d, 0, sizeof(d));
+  d.sp.n = n;
+  d.tiles_x = f.tiles_x;
+  d.tiles_y = f.tiles_y;
+  d.nz_chunk = f.chunk;
+  d.tail_from = f.tail_from;
+  d.tail_split = f.tail_split;
+  const fused::ItemPlanes ip(d, item);
+  *tile = ip.tile;
+  *z0 = ip.z0;
+  *planes = ip.left;
 }
 
 // Work items of a box's fused launch (and its tiling).  With z_chunk = 0
@@ -1410,7 +1433,7 @@ static int fused_slots(int precision, int w) {
 // ones.  At 256^3 in FP64 (1 block per unit, 387 column tiles): chunks of
 // 37 planes cost 11 rounds of 39 iterations (the last round 58% full: 429);
 // chunks of 128 planes, 3 full rounds of 130 and 6 chunks left over that
-// are cut into 42 parts of 4 planes, 396.
+// are cut into 32 parts of 4 planes, 396.
 int fused_balanced_chunk(int n, int tiles_xy, int slots) {
   const int cmin = std::min(n, kMinAutoChunk);
   int best = n;

@@ -147,6 +147,10 @@ struct FusedPlan {
   int width, tiles_x, tiles_y, chunk, items, tail_from, tail_split, grid;
 };
 FusedPlan fused_plan(const dhit_params &p);
+// The same for a device holding `slots` blocks of the kernel at once (no
+// device query), and the tile and planes [z0, z0 + planes) of one item.
+FusedPlan fused_plan_for(const dhit_params &p, int slots);
+void fused_item_planes(const FusedPlan &f, int n, int item, int *tile, int *z0, int *planes);
 void launch_init_equilibrium(dhit_box &b, const double *d_u, const double *d_drho, void *dst);
 void launch_moments(dhit_box &b, const void *f, double *d_drho, double *d_j, double *d_sums);
 // One pass of the LBE initial-state iteration on state f (in place): momentum
