@@ -61,12 +61,13 @@ int32_t guarded(F &&f) {
 // to 256 bytes' worth of elements plus a shift, so that the 19 arrays start
 // at staggered offsets modulo large powers of two (cell counts such as 256^3
 // would otherwise place all 19 streams on the same memory channels).  The
-// shift suits each kernel's access pattern (measured at 256^3): 1 KiB for the
-// LBE, whose 19 streams advance together (FP64 step 3% faster than with
-// 4 KiB), 16 KiB for the DUGKS march (1 KiB made it 4% slower).
+// shift suits each kernel's access pattern (measured at 256^3): 3 KiB for the
+// LBE, whose 19 streams advance together (in sweeps of 0.5 to 9 KiB the FP64
+// step was fastest at 3 KiB: 1% faster than at 1 KiB, 4% than at 4 KiB;
+// FP32 alike within 1%), 16 KiB for the DUGKS march (1 KiB made it 4% slower).
 int64_t padded_stride(int64_t ncell, size_t elem, int method) {
   const int64_t align = 256 / (int64_t)elem;
-  const int64_t shift = (method == DHIT_DUGKS ? 16384 : 1024) / (int64_t)elem;
+  const int64_t shift = (method == DHIT_DUGKS ? 16384 : 3072) / (int64_t)elem;
   return ((ncell + align - 1) / align) * align + shift;
 }
 
