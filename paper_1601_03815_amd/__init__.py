@@ -184,8 +184,9 @@ def step_boxes(boxes, nsteps=1):
 
 
 class Batch:
-    """Boxes of one method and precision advanced together: persistent
-    batched launches, autotuned, replayed from a captured hipGraph."""
+    """Boxes of one method and precision advanced together: one launch per
+    step over all of them (one block per work item or a persistent grid),
+    autotuned, replayed from a captured hipGraph."""
 
     def __init__(self, boxes, autotune=True, stream=None):
         self.boxes = list(boxes)

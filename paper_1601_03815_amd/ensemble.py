@@ -1,8 +1,8 @@
 """Batched ensembles of independent decaying-turbulence runs.
 
 An ensemble is many boxes (distinct seeds, mixed grid sizes) of one method
-and precision advanced together by `Batch` (one persistent launch per step,
-graph replays, autotuned grid).  Also runs the same boxes one launch per box
+and precision advanced together by `Batch` (one launch per step over all
+boxes, graph replays, autotuned grid).  Also runs the same boxes one launch per box
 for comparison, and averages energy spectra over the realisations of each
 grid size.
 """

@@ -4,7 +4,7 @@ Requests (grid size, method, number of steps, seed) arrive over time.  The
 scheduler admits a waiting request when its device memory fits the HBM
 budget and a slot is free, keeps every admitted run's populations resident
 on the device, and advances all active runs together: the runs of each
-method form one batch (one persistent launch per step for all of them, on
+method form one batch (one launch per step for all of them, on
 that method's stream, so the two methods' work overlaps on the device).
 The active set is re-formed whenever a run finishes or is admitted, between
 chunks of steps, so requests that arrive while others are running join
